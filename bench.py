@@ -1,0 +1,259 @@
+"""Benchmark of the four-directional 5x5 Sobel operator on one MI355X.
+
+Headline: uint8 8192x8192, magnitude only, replicate border -- Gpixel/s and
+the achieved fraction of HBM peak, with inputs resident in HBM.  Launches
+rotate over >= 1 GiB of distinct (src, mag) buffer sets so that the 256 MB
+Infinity Cache cannot serve them.  Secondary results (mixed-size batch in one
+persistent launch vs per-image launches, fp32 forward+backward, the size /
+output-type sweep) are reported in extra keys of the same JSON line.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--only u8|batched|f32|sweep]
+                [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "Gpixel/s + % of HBM peak, 4-dir 5x5 Sobel, uint8 8192² and mixed-size batch"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+N = 8192
+ROTATE_BYTES = 2 << 30         # >= 1 GiB of distinct buffers (Infinity Cache is 256 MB)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--only", choices=["u8", "batched", "f32", "sweep"], default=None)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    return p.parse_args()
+
+
+def time_launches(torch, fn, steps, warmup):
+    """Average ms per call of fn(i) over `steps` calls, HIP events on the current stream."""
+    for i in range(warmup):
+        fn(i)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for i in range(steps):
+        fn(i)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def image_sets(torch, img, dev, nsets, pitch=None):
+    h, w = img.shape
+    base = torch.from_numpy(img).to(dev)
+    srcs, mags = [], []
+    for _ in range(nsets):
+        s = torch.empty((h, w), dtype=torch.uint8, device=dev)
+        s.copy_(base)
+        srcs.append(s)
+        mags.append(torch.empty((h, w), dtype=torch.uint8, device=dev))
+    return srcs, mags
+
+
+def bench_u8(torch, api, synth, dev, steps, warmup):
+    img = synth.rect_image(N, N, 3)
+    nsets = max(2, ROTATE_BYTES // (2 * N * N))
+    srcs, mags = image_sets(torch, img, dev, nsets)
+
+    def step(i):
+        k = i % nsets
+        api.sobel4x5_u8(srcs[k], mag=mags[k])
+
+    ms = time_launches(torch, step, steps, warmup)
+    hot = time_launches(torch, lambda i: api.sobel4x5_u8(srcs[0], mag=mags[0]), steps, warmup)
+    px = N * N
+    res = {
+        "ms": ms, "gpx": px / (ms * 1e-3) / 1e9, "alg_bytes": 2 * px,
+        "hot_ms": hot, "nsets": nsets, "rotating_gib": nsets * 2 * px / 2 ** 30,
+    }
+    del srcs, mags
+    torch.cuda.empty_cache()
+    return res, img
+
+
+def bench_sweep(torch, api, synth, dev, steps, warmup):
+    out = {}
+    for n in (4096, 8192, 16384):
+        img = synth.rect_image(n, n, 3)
+        px = n * n
+        for mode in ("mag_u8", "dir_s16"):
+            per = 2 * px if mode == "mag_u8" else 9 * px
+            nsets = max(2, ROTATE_BYTES // per)
+            base = torch.from_numpy(img).to(dev)
+            srcs = [base.clone() for _ in range(nsets)]
+            if mode == "mag_u8":
+                outs = [torch.empty((n, n), dtype=torch.uint8, device=dev) for _ in range(nsets)]
+                fn = lambda i: api.sobel4x5_u8(srcs[i % nsets], mag=outs[i % nsets])
+            else:
+                outs = [[torch.empty((n, n), dtype=torch.int16, device=dev) for _ in range(4)]
+                        for _ in range(nsets)]
+                fn = lambda i: api.sobel4x5_u8(srcs[i % nsets], want_mag=False, dir_type=api.DIR_S16,
+                                               dirs=outs[i % nsets])
+            k = max(10, steps // (1 if n <= 8192 else 4))
+            ms = time_launches(torch, fn, k, max(3, warmup // 4))
+            gbs = per / (ms * 1e-3) / 1e9
+            out["%d_%s" % (n, mode)] = {"ms": round(ms, 5), "gpx_per_s": round(px / (ms * 1e-3) / 1e9, 2),
+                                        "alg_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                                        "bytes_per_px": per // px}
+            del srcs, outs, base
+            torch.cuda.empty_cache()
+    return out
+
+
+def bench_batched(torch, api, synth, dev, steps, warmup):
+    sizes = synth.batch_sizes(256, 77)
+    imgs = [synth.rect_image(h, w, 1000 + i) for i, (h, w) in enumerate(sizes)]
+    srcs, mags = [], []
+    for m in imgs:
+        h, w = m.shape
+        pitch = synth.round_up(w, 256)
+        flat = torch.empty(((h - 1) * pitch + w,), dtype=torch.uint8, device=dev)
+        v = flat.as_strided((h, w), (pitch, 1))
+        v.copy_(torch.from_numpy(m))
+        srcs.append(v)
+        mags.append(torch.empty((h, w), dtype=torch.uint8, device=dev))
+    px = sum(h * w for h, w in sizes)
+    plan = api.Plan(srcs, mags, autotune=True)
+    k = max(5, steps // 10)
+    ms_plan = time_launches(torch, lambda i: plan.launch(), k, 3)
+
+    def per_image(i):
+        for s, m in zip(srcs, mags):
+            api.sobel4x5_u8(s, mag=m)
+
+    ms_eager = time_launches(torch, per_image, k, 2)
+    # the same 256 launches captured in one graph (launch cost removed)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        per_image(0)
+    ms_graph = time_launches(torch, lambda i: g.replay(), k, 2)
+    info = plan.info()
+    res = {"images": 256, "total_px": px, "bytes_per_px": 2,
+           "persistent_graph_ms": round(ms_plan, 4), "persistent_gpx_per_s": round(px / ms_plan / 1e6, 2),
+           "per_image_eager_ms": round(ms_eager, 4), "per_image_eager_gpx_per_s": round(px / ms_eager / 1e6, 2),
+           "per_image_graph_ms": round(ms_graph, 4), "per_image_graph_gpx_per_s": round(px / ms_graph / 1e6, 2),
+           "speedup_vs_eager": round(ms_eager / ms_plan, 3), "speedup_vs_graph": round(ms_graph / ms_plan, 3),
+           "hbm_frac": round(2 * px / (ms_plan * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "tile": info}
+    plan.close()
+    del srcs, mags, g
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_f32(torch, api, synth, dev, steps, warmup):
+    B, H, W = 32, 1024, 1024
+    x = torch.from_numpy(synth.float_batch(B, H, W)).to(dev)
+    M = torch.empty_like(x)
+    gm = torch.full_like(x, 1.0 / x.numel())
+    dx = torch.empty_like(x)
+    k = max(5, steps // 10)
+    ms_f = time_launches(torch, lambda i: api.sobel4x5_f32_fwd(x, out=M), k, 3)
+    ms_b = time_launches(torch, lambda i: api.sobel4x5_f32_bwd(x, gm, out=dx), k, 3)
+    px = B * H * W
+    res = {"batch": B, "H": H, "W": W, "fwd_ms": round(ms_f, 4), "bwd_ms": round(ms_b, 4),
+           "fwd_bwd_gpx_per_s": round(px / ((ms_f + ms_b) * 1e-3) / 1e9, 2),
+           "fwd_GBps": round(8 * px / (ms_f * 1e-3) / 1e9, 1), "bwd_GBps": round(12 * px / (ms_b * 1e-3) / 1e9, 1),
+           "fwd_bwd_hbm_frac": round(20 * px / ((ms_f + ms_b) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del x, M, gm, dx
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(img):
+    """The CPU oracle (as it stands) on the same 8192x8192 image, all cores."""
+    import oracle
+    oracle.build()
+    cores = len(os.sched_getaffinity(0))
+    runs = []
+    t_total = 0.0
+    while len(runs) < 3 and (t_total < 10.0 or not runs):
+        t0 = time.perf_counter()
+        oracle.sobel_u8(img, want_dir=False, nthreads=cores)
+        dt = time.perf_counter() - t0
+        runs.append(dt)
+        t_total += dt
+    best = min(runs)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": round(img.size / best / 1e9, 4), "unit": "Gpixel/s", "cores": cores, "kind": "oracle",
+            "sample": "the full 8192x8192 uint8 image, magnitude only, %d run(s), best %.2f s; CPU %s"
+                      % (len(runs), best, model)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(got --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from paper_2305_00515_amd import api, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    line = {"metric": METRIC, "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+            "data": "synthetic"}
+    only = args.only
+    img = None
+    if only in (None, "u8"):
+        log("u8 8192x8192 magnitude: %d steps" % args.steps)
+        r, img = bench_u8(torch, api, synth, dev, args.steps, args.warmup)
+        achieved = r["alg_bytes"] / (r["ms"] * 1e-3) / 1e9
+        line.update({
+            "value": round(r["gpx"], 2), "ms_per_step": round(r["ms"], 5),
+            "config": {"workload": "uint8 8192x8192 four-directional 5x5 Sobel, uint8 magnitude only, "
+                                   "replicate border, one image per step",
+                       "image": "rect_image(8192, 8192, seed=3): uniform noise + 20 filled rectangles",
+                       "bytes_per_px": 2, "rotating_buffers_gib": round(r["rotating_gib"], 2),
+                       "hot_same_buffer_ms": round(r["hot_ms"], 5)},
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                         "kernel": "k_u8_single<16,0,aligned,mag-only>",
+                         "alg_bytes_per_launch": r["alg_bytes"]},
+        })
+    if only in (None, "sweep"):
+        log("sweep")
+        line["sweep"] = bench_sweep(torch, api, synth, dev, args.steps, args.warmup)
+    if only in (None, "batched"):
+        log("batched 256 images")
+        line["batched"] = bench_batched(torch, api, synth, dev, args.steps, args.warmup)
+    if only in (None, "f32"):
+        log("fp32 32x1024^2 fwd+bwd")
+        line["f32"] = bench_f32(torch, api, synth, dev, args.steps, args.warmup)
+    if img is not None and not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(img)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,205 @@
+/*
+ * sobel4x5.h -- C ABI of the MI355X (gfx950) four-directional 5x5 Sobel library.
+ *
+ * The operator (Chang et al., "Multi-directional Sobel operator kernel on
+ * GPUs", Sec. 3.1): four fixed 5x5 integer filters, Eq. (sobel5_1) --
+ * 0 deg (Gx), 45 deg (Gd), 90 deg (Gy), 135 deg (Gdt) -- are applied to every
+ * pixel of an 8-bit grayscale image as a correlation (tap (i, j) of a printed
+ * matrix multiplies the pixel at row offset i-2, column offset j-2, the way
+ * the row filters Eq. (Fx) and Eq. (Gd+) of Sec. 4.3 index the pixels), and
+ * combined into the root-sum-of-squares magnitude of Eq. (sobel5_2).
+ *
+ * Conventions shared by every entry point
+ *   - Buffers named src/dst/mag/dir/grad are DEVICE pointers owned by the
+ *     caller.  Nothing here frees them.  Descriptor arrays and the outputs
+ *     struct are HOST memory, read during the call only.
+ *   - Pitches and strides are in BYTES.  A row pitch must be at least the
+ *     row's width in bytes; any larger value is accepted.  Aligned rows
+ *     (16-byte base and pitch) take the fast path; anything else takes a
+ *     slower path with identical results.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued asynchronously on it; device faults surface at the
+ *     caller's next synchronisation.
+ *   - Every argument is checked on the host before anything is enqueued, so
+ *     an error return means no work was queued.  Launch failures map to
+ *     SOBEL4X5_EHIP.  sobel4x5_last_error() gives a human-readable detail
+ *     for the calling thread's last failed call.
+ *   - Inputs and outputs must not overlap (the stencil reads neighbours).
+ *   - Calls are thread-safe; a plan must not be launched from two threads at
+ *     the same time.
+ *
+ * Borders (Sec. 4.3 leaves the padding rule to an earlier work)
+ *   SOBEL4X5_BORDER_REPLICATE : clamp-to-edge; output is H x W; any H, W >= 1.
+ *   SOBEL4X5_BORDER_VALID     : the paper's shrink by 2r = 4 (Sec. 4.3, data
+ *                               flow); output is (H-4) x (W-4) and
+ *                               out(y, x) = replicate(y+2, x+2); H, W >= 5.
+ *
+ * uint8 magnitude: min(255, round-to-nearest(sqrt(S))), S = Gx^2 + Gd^2 +
+ * Gy^2 + Gdt^2 -- exact (integer S never sits on a half-way point).
+ */
+#ifndef SOBEL4X5_H
+#define SOBEL4X5_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SOBEL4X5_VERSION 100
+
+/* status codes */
+#define SOBEL4X5_OK 0
+#define SOBEL4X5_EINVAL 1          /* bad argument; nothing enqueued          */
+#define SOBEL4X5_EUNSUPPORTED 2    /* valid request this build cannot serve   */
+#define SOBEL4X5_EHIP 3            /* a HIP runtime call or launch failed     */
+#define SOBEL4X5_ENOMEM 4          /* device or host allocation failed        */
+
+/* border rules */
+#define SOBEL4X5_BORDER_REPLICATE 0
+#define SOBEL4X5_BORDER_VALID 1
+
+/* directional output element types */
+#define SOBEL4X5_DIR_NONE 0
+#define SOBEL4X5_DIR_S16 1         /* int16 planes (exact: |G| <= 12240)      */
+#define SOBEL4X5_DIR_S32 2         /* int32 planes                            */
+
+/*
+ * Outputs of one uint8 image.  Host struct.
+ *   mag       : Ho rows of Wo bytes, row r at mag + r*mag_pitch; NULL = none.
+ *   dir[k]    : plane k (0 = 0 deg Gx, 1 = 45 deg Gd, 2 = 90 deg Gy,
+ *               3 = 135 deg Gdt), Ho rows of Wo elements of dir_type, row r at
+ *               (char*)dir[k] + r*dir_pitch.  Used iff dir_type != DIR_NONE,
+ *               and then all four must be non-NULL.
+ * At least one of mag / dir must be requested.
+ */
+typedef struct sobel4x5_outputs {
+    uint8_t *mag;
+    int64_t mag_pitch;
+    void *dir[4];
+    int64_t dir_pitch;
+    int32_t dir_type;
+} sobel4x5_outputs;
+
+/*
+ * sobel4x5_u8 -- Eq. (sobel5_1) + Eq. (sobel5_2) on one uint8 image.
+ *   src        : H rows of W bytes, row r at src + r*src_pitch (device).
+ *   width      : W >= 1 (>= 5 for VALID); height: H likewise.
+ *   border     : SOBEL4X5_BORDER_*.
+ *   out        : host struct, see above.
+ * Integer arithmetic throughout; results are bit-exact.
+ */
+int sobel4x5_u8(const uint8_t *src, int32_t width, int32_t height, int64_t src_pitch,
+                int32_t border, const sobel4x5_outputs *out, void *stream);
+
+/* Host-only argument check of sobel4x5_u8 (never touches the GPU). */
+int sobel4x5_validate_u8(const uint8_t *src, int32_t width, int32_t height, int64_t src_pitch,
+                         int32_t border, const sobel4x5_outputs *out);
+
+/*
+ * Batched uint8 magnitudes: many images of uneven sizes in ONE launch of a
+ * persistent work-queue kernel (not in the paper; it applies the same integer
+ * arithmetic per image).
+ *   sobel4x5_image : host descriptor; src/mag device pointers, pitches in bytes.
+ */
+typedef struct sobel4x5_image {
+    const uint8_t *src;
+    uint8_t *mag;
+    int32_t width;
+    int32_t height;
+    int64_t src_pitch;
+    int64_t mag_pitch;
+} sobel4x5_image;
+
+typedef struct sobel4x5_plan_s *sobel4x5_plan;
+
+#define SOBEL4X5_PLAN_AUTOTUNE 1u  /* time candidate tile shapes, keep the fastest
+                                      that is bit-exact against the default   */
+#define SOBEL4X5_PLAN_NO_GRAPH 2u  /* launch the kernel directly, no hipGraph */
+
+/*
+ * sobel4x5_plan_create -- build a reusable plan for a fixed set of images.
+ *   imgs/count : host array of count >= 1 descriptors (copied).
+ *   border     : SOBEL4X5_BORDER_*.
+ *   flags      : SOBEL4X5_PLAN_* bits.
+ *   out        : receives the plan handle.
+ * Allocates device memory for the tile table and queue counters (ENOMEM on
+ * failure), uploads them, selects the tile shape (autotuned with
+ * SOBEL4X5_PLAN_AUTOTUNE, which runs and synchronises the device), and
+ * captures the launch in a hipGraph.  The images' contents are not read here
+ * except during autotuning, which writes the mag buffers.
+ */
+int sobel4x5_plan_create(const sobel4x5_image *imgs, int32_t count, int32_t border,
+                         uint32_t flags, sobel4x5_plan *out);
+
+/* Enqueue the plan's work on `stream` (graph launch).  The queue counters
+ * reset themselves at the end of every launch, so launches can repeat. */
+int sobel4x5_plan_launch(sobel4x5_plan plan, void *stream);
+
+/* Tile shape the plan uses: pixels per lane, rows per tile, waves per
+ * workgroup, and the persistent grid size.  Any pointer may be NULL. */
+int sobel4x5_plan_info(sobel4x5_plan plan, int32_t *px_per_lane, int32_t *rows_per_tile,
+                       int32_t *waves_per_group, int32_t *grid);
+
+/* Free the plan (device memory, graph).  Waits for nothing: the caller must
+ * make sure no launch of it is still running. */
+int sobel4x5_plan_destroy(sobel4x5_plan plan);
+
+/* One-shot batched call: builds (or reuses a cached) plan for these images
+ * and launches it on `stream`.  Equivalent to plan_create + plan_launch. */
+int sobel4x5_batched(const sobel4x5_image *imgs, int32_t count, int32_t border, void *stream);
+
+/* Host-only argument check of a batch (never touches the GPU). */
+int sobel4x5_validate_batch(const sobel4x5_image *imgs, int32_t count, int32_t border);
+
+/*
+ * Real-valued path (not in the paper): the same correlation in fp32 on a
+ * batch of images, for use as a differentiable edge loss.
+ *
+ * sobel4x5_f32_fwd -- M = sqrt(Gx^2 + Gd^2 + Gy^2 + Gdt^2) per pixel, fp32
+ * arithmetic.  Each response is summed as differences of opposite taps, so a
+ * flat 5x5 window gives exactly M = 0.
+ *   src  : batch images of height rows x width floats; image b, row r at
+ *          (char*)src + b*src_bstride + r*src_pitch.
+ *   mag  : batch images of Ho x Wo floats, same addressing with mag_* strides.
+ */
+int sobel4x5_f32_fwd(const float *src, int32_t batch, int32_t width, int32_t height,
+                     int64_t src_pitch, int64_t src_bstride, int32_t border,
+                     float *mag, int64_t mag_pitch, int64_t mag_bstride, void *stream);
+
+/*
+ * sobel4x5_f32_bwd -- adjoint of sobel4x5_f32_fwd: given grad_mag = dL/dM
+ * (Ho x Wo per image), writes grad_src = dL/dsrc (H x W per image,
+ * overwritten).  u_k = grad_mag * G_k / M where M > 0 and 0 where M = 0; each
+ * u_k is spread back through the transposed filter, and the contributions
+ * that the replicate border sent to clamped pixels are folded onto the edge
+ * rows and columns.  G is recomputed from src (no saved state).
+ */
+int sobel4x5_f32_bwd(const float *src, int64_t src_pitch, int64_t src_bstride,
+                     const float *grad_mag, int64_t g_pitch, int64_t g_bstride,
+                     int32_t batch, int32_t width, int32_t height, int32_t border,
+                     float *grad_src, int64_t gs_pitch, int64_t gs_bstride, void *stream);
+
+/* Host-only argument check shared by the two fp32 calls (never touches the
+ * GPU).  Pass grad pointers as NULL and their strides as 0 to check a
+ * forward call. */
+int sobel4x5_validate_f32(const float *src, int32_t batch, int32_t width, int32_t height,
+                          int64_t src_pitch, int64_t src_bstride, int32_t border,
+                          const float *out, int64_t out_pitch, int64_t out_bstride);
+
+/*
+ * Diagnostic: the library's uint8 rounding of the magnitude, applied to n
+ * given values of 2*S (S = sum of the four squared responses, so 2*S is
+ * even).  out[i] = min(255, round(sqrt(s2[i] / 2))).  Device pointers.
+ */
+int sobel4x5_debug_round_mag(const int32_t *s2, uint8_t *out, int64_t n, void *stream);
+
+const char *sobel4x5_status_string(int status);
+const char *sobel4x5_last_error(void);
+int sobel4x5_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SOBEL4X5_H */

@@ -55,6 +55,10 @@ def _load():
         lib.oracle_f64_fwd.restype = I
         lib.oracle_f64_bwd.argtypes = [P, P, I, I, I, I, P, P, I]
         lib.oracle_f64_bwd.restype = I
+        lib.oracle_f64_bwd_scale.argtypes = [P, P, I, I, I, I, P, P, I]
+        lib.oracle_f64_bwd_scale.restype = I
+        lib.oracle_f64_fwd_scale.argtypes = [P, I, I, I, I, P, P, I]
+        lib.oracle_f64_fwd_scale.restype = I
         lib.oracle_weights.argtypes = [P]
         lib.oracle_weights.restype = None
         lib.oracle_round_sqrt.argtypes = [ctypes.c_int64]
@@ -166,3 +170,37 @@ def sobel_f64_bwd(x: np.ndarray, g: np.ndarray, border: int = REPLICATE, *, weig
     if rc != 0:
         raise ValueError("oracle_f64_bwd rejected its arguments (rc=%d)" % rc)
     return dx
+
+
+def sobel_f64_bwd_scale(x: np.ndarray, g: np.ndarray, border: int = REPLICATE, *, weights=None,
+                        nthreads: int = 0) -> np.ndarray:
+    """Per-input-pixel sum of |term| of the adjoint's sum (tolerance scale A(p))."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    if x.ndim == 2:
+        x = x[None]
+        g = g[None]
+    b, h, w = x.shape
+    a = np.empty((b, h, w), np.float64)
+    wt = _weights_arg(weights)
+    rc = _load().oracle_f64_bwd_scale(_ptr(x), _ptr(g), b, h, w, border, _ptr(a), _ptr(wt),
+                                      int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_f64_bwd_scale rejected its arguments (rc=%d)" % rc)
+    return a
+
+
+def sobel_f64_fwd_scale(x: np.ndarray, border: int = REPLICATE, *, weights=None,
+                        nthreads: int = 0) -> np.ndarray:
+    """Per-output-pixel max_k sum_t |K_k[t] x_t| (tolerance scale of the forward)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.ndim == 2:
+        x = x[None]
+    b, h, w = x.shape
+    ho, wo = out_shape(h, w, border)
+    s = np.empty((b, ho, wo), np.float64)
+    wt = _weights_arg(weights)
+    rc = _load().oracle_f64_fwd_scale(_ptr(x), b, h, w, border, _ptr(s), _ptr(wt), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_f64_fwd_scale rejected its arguments (rc=%d)" % rc)
+    return s

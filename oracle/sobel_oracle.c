@@ -299,9 +299,13 @@ int oracle_f64_fwd(const double *x, int B, int H, int W, int border,
  * every direction k, u_k(q) = g(q) * G_k(q) / M(q); then every tap (i, j) of
  * filter k adds K_k[i][j] * u_k(q) to the input pixel it read in the forward
  * pass (the same clamped index).  Where M(q) = 0 nothing is added.
+ *
+ * With absmode set, it adds |K_k[i][j]| * |u_k(q)| instead: the magnitude of
+ * the sum's terms at every input pixel, which scales the rounding error any
+ * summation order can make (used for test tolerances).
  */
-int oracle_f64_bwd(const double *x, const double *g, int B, int H, int W, int border,
-                   double *dx, const int32_t *weights, int nthreads)
+static int bwd_impl(const double *x, const double *g, int B, int H, int W, int border,
+                    double *dx, const int32_t *weights, int nthreads, int absmode)
 {
     int Wo, Ho;
     if (!x || !g || !dx || B < 0 || out_dims(W, H, border, &Wo, &Ho) != OR_OK)
@@ -329,14 +333,70 @@ int oracle_f64_bwd(const double *x, const double *g, int B, int H, int W, int bo
                 }
                 for (int k = 0; k < 4; ++k) {
                     double u = gb[y * Wo + xo] * G[k] / M;
+                    if (absmode)
+                        u = fabs(u);
                     for (int i = 0; i < 5; ++i) {
                         long yy = clampl(yc + i - 2, 0, H - 1);
                         for (int j = 0; j < 5; ++j) {
                             long xx = clampl(xc + j - 2, 0, W - 1);
-                            db[yy * W + xx] += (double)K[(k * 5 + i) * 5 + j] * u;
+                            double w = (double)K[(k * 5 + i) * 5 + j];
+                            db[yy * W + xx] += (absmode ? fabs(w) : w) * u;
                         }
                     }
                 }
+            }
+        }
+    }
+    return OR_OK;
+}
+
+int oracle_f64_bwd(const double *x, const double *g, int B, int H, int W, int border,
+                   double *dx, const int32_t *weights, int nthreads)
+{
+    return bwd_impl(x, g, B, H, W, border, dx, weights, nthreads, 0);
+}
+
+int oracle_f64_bwd_scale(const double *x, const double *g, int B, int H, int W, int border,
+                         double *A, const int32_t *weights, int nthreads)
+{
+    return bwd_impl(x, g, B, H, W, border, A, weights, nthreads, 1);
+}
+
+/*
+ * Scale of the forward's rounding error at every output pixel:
+ * max over the four filters of sum_t |K_k[t] * x(tap t)|.
+ */
+int oracle_f64_fwd_scale(const double *x, int B, int H, int W, int border, double *scale,
+                         const int32_t *weights, int nthreads)
+{
+    int Wo, Ho;
+    if (!x || !scale || B < 0 || out_dims(W, H, border, &Wo, &Ho) != OR_OK)
+        return OR_EINVAL;
+    const int32_t *K = pick_weights(weights);
+    const long plane_in = (long)W * H, plane_out = (long)Wo * Ho;
+#pragma omp parallel for collapse(2) schedule(static) num_threads(nthreads > 0 ? nthreads : omp_default_threads())
+    for (long b = 0; b < B; ++b) {
+        for (long y = 0; y < Ho; ++y) {
+            for (long xo = 0; xo < Wo; ++xo) {
+                long yc = y, xc = xo;
+                if (border == OR_BORDER_VALID) {
+                    yc += 2;
+                    xc += 2;
+                }
+                double best = 0.0;
+                for (int k = 0; k < 4; ++k) {
+                    double acc = 0.0;
+                    for (int i = 0; i < 5; ++i) {
+                        long yy = clampl(yc + i - 2, 0, H - 1);
+                        for (int j = 0; j < 5; ++j) {
+                            long xx = clampl(xc + j - 2, 0, W - 1);
+                            acc += fabs((double)K[(k * 5 + i) * 5 + j] * x[b * plane_in + yy * W + xx]);
+                        }
+                    }
+                    if (acc > best)
+                        best = acc;
+                }
+                scale[b * plane_out + y * Wo + xo] = best;
             }
         }
     }

@@ -1,0 +1,283 @@
+"""ctypes binding of libsobel4x5.so (the C ABI of include/sobel4x5.h).
+
+Argument marshalling only: every function checks tensor devices/dtypes,
+converts them to raw device pointers and byte pitches, and calls the library
+on torch's current HIP stream.  All arithmetic happens in the HIP kernels.
+The library is required: importing this module on a machine where it cannot
+be loaded raises, and there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import torch
+
+_PKG = Path(__file__).resolve().parent
+LIB_PATH = _PKG / "libsobel4x5.so"
+
+BORDER_REPLICATE = 0
+BORDER_VALID = 1
+DIR_NONE = 0
+DIR_S16 = 1
+DIR_S32 = 2
+PLAN_AUTOTUNE = 1
+PLAN_NO_GRAPH = 2
+
+OK, EINVAL, EUNSUPPORTED, EHIP, ENOMEM = 0, 1, 2, 3, 4
+
+
+class SobelError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__("%s failed (%d): %s" % (where, code, detail))
+        self.code = code
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("mag", ctypes.c_void_p), ("mag_pitch", ctypes.c_int64),
+                ("dir", ctypes.c_void_p * 4), ("dir_pitch", ctypes.c_int64),
+                ("dir_type", ctypes.c_int32)]
+
+
+class Image(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("mag", ctypes.c_void_p),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("src_pitch", ctypes.c_int64), ("mag_pitch", ctypes.c_int64)]
+
+
+def _load() -> ctypes.CDLL:
+    if not LIB_PATH.exists():
+        raise ImportError("libsobel4x5.so is not built (run __graft_entry__.build() or "
+                          "python -m paper_2305_00515_amd.build)")
+    lib = ctypes.CDLL(str(LIB_PATH))
+    P, I32, I64, U32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    sig = {
+        "sobel4x5_u8": [P, I32, I32, I64, I32, ctypes.POINTER(Outputs), P],
+        "sobel4x5_validate_u8": [P, I32, I32, I64, I32, ctypes.POINTER(Outputs)],
+        "sobel4x5_plan_create": [ctypes.POINTER(Image), I32, I32, U32, ctypes.POINTER(P)],
+        "sobel4x5_plan_launch": [P, P],
+        "sobel4x5_plan_info": [P] + [ctypes.POINTER(I32)] * 4,
+        "sobel4x5_plan_destroy": [P],
+        "sobel4x5_batched": [ctypes.POINTER(Image), I32, I32, P],
+        "sobel4x5_validate_batch": [ctypes.POINTER(Image), I32, I32],
+        "sobel4x5_f32_fwd": [P, I32, I32, I32, I64, I64, I32, P, I64, I64, P],
+        "sobel4x5_f32_bwd": [P, I64, I64, P, I64, I64, I32, I32, I32, I32, P, I64, I64, P],
+        "sobel4x5_validate_f32": [P, I32, I32, I32, I64, I64, I32, P, I64, I64],
+        "sobel4x5_debug_round_mag": [P, P, I64, P],
+        "sobel4x5_status_string": [ctypes.c_int],
+        "sobel4x5_last_error": [],
+        "sobel4x5_version": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.sobel4x5_status_string.restype = ctypes.c_char_p
+    lib.sobel4x5_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != OK:
+        raise SobelError(rc, where, lib.sobel4x5_last_error().decode())
+
+
+def _stream(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _need_cuda(t: torch.Tensor, dtype, name: str) -> None:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a GPU tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
+
+
+def _rows(t: torch.Tensor, name: str):
+    """(height, width, pitch bytes) of a 2-D tensor with unit column stride."""
+    if t.dim() != 2 or (t.size(1) > 1 and t.stride(1) != 1):
+        raise ValueError("%s must be 2-D with unit column stride" % name)
+    return t.size(0), t.size(1), t.stride(0) * t.element_size()
+
+
+def out_shape(h: int, w: int, border: int):
+    return (h, w) if border == BORDER_REPLICATE else (h - 4, w - 4)
+
+
+def sobel4x5_u8(src: torch.Tensor, border: int = BORDER_REPLICATE, *, mag: torch.Tensor | None = None,
+                want_mag: bool = True, dir_type: int = DIR_NONE, dirs: list | None = None):
+    """uint8 image (H, W) on the GPU -> (mag uint8 (Ho, Wo) or None, [4 planes] or None).
+
+    Planes are 0 deg Gx, 45 deg Gd, 90 deg Gy, 135 deg Gdt as int16 (DIR_S16)
+    or int32 (DIR_S32).  Output tensors may be passed in (any row pitch).
+    """
+    _need_cuda(src, torch.uint8, "src")
+    h, w, pitch = _rows(src, "src")
+    ho, wo = out_shape(h, w, border)
+    if want_mag and mag is None:
+        mag = torch.empty((max(ho, 0), max(wo, 0)), dtype=torch.uint8, device=src.device)
+    out = Outputs()
+    if want_mag or mag is not None:
+        _need_cuda(mag, torch.uint8, "mag")
+        if tuple(mag.shape) != (ho, wo):
+            raise ValueError("mag must have shape %s, got %s" % ((ho, wo), tuple(mag.shape)))
+        out.mag = mag.data_ptr()
+        out.mag_pitch = _rows(mag, "mag")[2]
+    if dir_type != DIR_NONE:
+        dt = torch.int16 if dir_type == DIR_S16 else torch.int32
+        if dirs is None:
+            dirs = [torch.empty((ho, wo), dtype=dt, device=src.device) for _ in range(4)]
+        pitches = set()
+        if len(dirs) != 4:
+            raise ValueError("need four directional planes")
+        for k, d in enumerate(dirs):
+            _need_cuda(d, dt, "dirs[%d]" % k)
+            if tuple(d.shape) != (ho, wo):
+                raise ValueError("dirs[%d] must have shape %s" % (k, (ho, wo)))
+            out.dir[k] = d.data_ptr()
+            pitches.add(_rows(d, "dirs[%d]" % k)[2])
+        if len(pitches) != 1:
+            raise ValueError("all four directional planes must share one row pitch")
+        out.dir_pitch = pitches.pop()
+    out.dir_type = dir_type
+    _check(lib.sobel4x5_u8(src.data_ptr(), w, h, pitch, border, ctypes.byref(out), _stream(src)),
+           "sobel4x5_u8")
+    return (mag if (want_mag or out.mag) else None), (dirs if dir_type != DIR_NONE else None)
+
+
+def _images(srcs, mags, border):
+    if len(srcs) != len(mags) or not srcs:
+        raise ValueError("need equally many (>= 1) sources and outputs")
+    arr = (Image * len(srcs))()
+    for i, (s, m) in enumerate(zip(srcs, mags)):
+        _need_cuda(s, torch.uint8, "srcs[%d]" % i)
+        _need_cuda(m, torch.uint8, "mags[%d]" % i)
+        h, w, p = _rows(s, "srcs[%d]" % i)
+        if tuple(m.shape) != out_shape(h, w, border):
+            raise ValueError("mags[%d] must have shape %s" % (i, out_shape(h, w, border)))
+        arr[i].src = s.data_ptr()
+        arr[i].mag = m.data_ptr()
+        arr[i].width = w
+        arr[i].height = h
+        arr[i].src_pitch = p
+        arr[i].mag_pitch = _rows(m, "mags[%d]" % i)[2]
+    return arr
+
+
+class Plan:
+    """A reusable batched plan over fixed (src, mag) tensor pairs.
+
+    The tensors are referenced, not copied: keep them alive (the plan holds
+    references) and do not reallocate them while the plan exists.
+    """
+
+    def __init__(self, srcs, mags, border: int = BORDER_REPLICATE, autotune: bool = False,
+                 graph: bool = True):
+        self._keep = (list(srcs), list(mags))
+        self._arr = _images(self._keep[0], self._keep[1], border)
+        self.device = self._keep[0][0].device
+        flags = (PLAN_AUTOTUNE if autotune else 0) | (0 if graph else PLAN_NO_GRAPH)
+        h = ctypes.c_void_p()
+        _check(lib.sobel4x5_plan_create(self._arr, len(self._arr), border, flags, ctypes.byref(h)),
+               "sobel4x5_plan_create")
+        self._h = h
+
+    def launch(self) -> None:
+        _check(lib.sobel4x5_plan_launch(self._h, _stream(self._keep[0][0])), "sobel4x5_plan_launch")
+
+    def info(self) -> dict:
+        vals = [ctypes.c_int32() for _ in range(4)]
+        _check(lib.sobel4x5_plan_info(self._h, *[ctypes.byref(v) for v in vals]), "sobel4x5_plan_info")
+        return dict(zip(("px_per_lane", "rows_per_tile", "waves_per_group", "grid"),
+                        (v.value for v in vals)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _check(lib.sobel4x5_plan_destroy(self._h), "sobel4x5_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) and torch is not None:
+                torch.cuda.synchronize(self.device)
+                lib.sobel4x5_plan_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+def sobel4x5_batched(srcs, mags=None, border: int = BORDER_REPLICATE):
+    """Magnitudes of many uint8 images of uneven sizes in one persistent launch."""
+    if mags is None:
+        mags = []
+        for s in srcs:
+            ho, wo = out_shape(s.size(0), s.size(1), border)
+            mags.append(torch.empty((ho, wo), dtype=torch.uint8, device=s.device))
+    arr = _images(list(srcs), list(mags), border)
+    _check(lib.sobel4x5_batched(arr, len(arr), border, _stream(srcs[0])), "sobel4x5_batched")
+    return mags
+
+
+def _f32_geom(t: torch.Tensor, name: str):
+    if t.dim() == 2:
+        t = t.unsqueeze(0)
+    if t.dim() != 3 or (t.size(2) > 1 and t.stride(2) != 1):
+        raise ValueError("%s must be (B, H, W) or (H, W) with unit column stride" % name)
+    return t, t.size(0), t.size(1), t.size(2), t.stride(1) * 4, t.stride(0) * 4
+
+
+def sobel4x5_f32_fwd(x: torch.Tensor, border: int = BORDER_REPLICATE, out: torch.Tensor | None = None):
+    """fp32 magnitude M (B, Ho, Wo) of x (B, H, W) (or (H, W))."""
+    _need_cuda(x, torch.float32, "x")
+    x3, b, h, w, pitch, bstride = _f32_geom(x, "x")
+    ho, wo = out_shape(h, w, border)
+    if out is None:
+        out = torch.empty((b, ho, wo), dtype=torch.float32, device=x.device)
+    _need_cuda(out, torch.float32, "out")
+    o3, _, _, _, op, ob = _f32_geom(out, "out")
+    if tuple(o3.shape) != (b, ho, wo):
+        raise ValueError("out must have shape %s" % ((b, ho, wo),))
+    _check(lib.sobel4x5_f32_fwd(x3.data_ptr(), b, w, h, pitch, bstride, border, o3.data_ptr(), op, ob,
+                                _stream(x)), "sobel4x5_f32_fwd")
+    return out if x.dim() == 3 else out.view(ho, wo)
+
+
+def sobel4x5_f32_bwd(x: torch.Tensor, grad_mag: torch.Tensor, border: int = BORDER_REPLICATE,
+                     out: torch.Tensor | None = None):
+    """dL/dx (B, H, W) given dL/dM (B, Ho, Wo)."""
+    _need_cuda(x, torch.float32, "x")
+    _need_cuda(grad_mag, torch.float32, "grad_mag")
+    x3, b, h, w, pitch, bstride = _f32_geom(x, "x")
+    g3, gb, gh, gw, gp, gbs = _f32_geom(grad_mag, "grad_mag")
+    if (gb, gh, gw) != (b,) + out_shape(h, w, border):
+        raise ValueError("grad_mag shape does not match the output shape")
+    if out is None:
+        out = torch.empty((b, h, w), dtype=torch.float32, device=x.device)
+    _need_cuda(out, torch.float32, "out")
+    o3, _, _, _, op, ob = _f32_geom(out, "out")
+    if tuple(o3.shape) != (b, h, w):
+        raise ValueError("out must have shape %s" % ((b, h, w),))
+    _check(lib.sobel4x5_f32_bwd(x3.data_ptr(), pitch, bstride, g3.data_ptr(), gp, gbs, b, w, h, border,
+                                o3.data_ptr(), op, ob, _stream(x)), "sobel4x5_f32_bwd")
+    return out if x.dim() == 3 else out.view(h, w)
+
+
+def debug_round_mag(s2: torch.Tensor) -> torch.Tensor:
+    """The library's uint8 rounding applied to values of 2*S (int32 tensor)."""
+    _need_cuda(s2, torch.int32, "s2")
+    s2 = s2.contiguous()
+    out = torch.empty(s2.shape, dtype=torch.uint8, device=s2.device)
+    _check(lib.sobel4x5_debug_round_mag(s2.data_ptr(), out.data_ptr(), s2.numel(), _stream(s2)),
+           "sobel4x5_debug_round_mag")
+    return out
+
+
+def status_string(code: int) -> str:
+    return lib.sobel4x5_status_string(code).decode()
+
+
+def version() -> int:
+    return lib.sobel4x5_version()

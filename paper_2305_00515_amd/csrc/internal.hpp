@@ -1,0 +1,81 @@
+// Internal declarations shared by the C-ABI layer (sobel4x5_api.cpp) and the
+// HIP kernel translation units.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace s4x5 {
+
+// One uint8 image as the kernels see it.  Output pixel (yo, xo) is the
+// operator centred on input pixel (yo + off, xo + off): off = 0 for the
+// replicate border, 2 for the valid border.
+struct U8Job {
+    const uint8_t *src;
+    uint8_t *mag;          // may be null
+    void *dir[4];          // used iff dir_type != 0
+    int64_t src_pitch;
+    int64_t mag_pitch;
+    int64_t dir_pitch;
+    int32_t W, H;          // input size
+    int32_t Wo, Ho;        // output size
+    int32_t dir_type;      // 0 none, 1 int16, 2 int32
+    int32_t ntx;           // tile columns (tile width = 16 lanes * px_per_lane)
+    int32_t nty4;          // ceil(tile rows / 4): a wave takes 4 stacked tiles
+    int32_t nty;           // tile rows
+    int32_t nwt;           // wave tiles = ntx * nty4
+    int32_t mag_vec;       // mag rows 16-byte aligned: vector stores allowed
+    int32_t dir_vec;       // dir rows 16-byte aligned
+};
+
+// Tile shape.  A 16-lane group owns a tile of (16 * ppl) columns x th rows;
+// a wave owns 4 vertically stacked tiles.
+struct U8Shape {
+    int ppl;   // pixels per lane: 8 or 16
+    int th;    // rows per tile
+    int wpg;   // waves per workgroup: 2, 4 or 8
+};
+
+// True when the fast (vector-load) kernel may read this image: 16-byte
+// aligned base and pitch.
+bool u8_rows_aligned(const U8Job &j);
+
+// Fills the tiling fields of `j` for shape `s`.
+void u8_tile(U8Job &j, const U8Shape &s);
+
+// Single image: one launch, one wave per wave-tile.
+hipError_t launch_u8_single(const U8Job &j, int border_valid, const U8Shape &s,
+                            hipStream_t stream);
+
+// Batched persistent launch (`aligned`: every image has 16-byte aligned src
+// rows).  `jobs` (device) holds `count` images whose
+// wave-tile counts have exclusive prefix sums `wt_prefix` (device, count+1
+// entries); `queue` (device, 2 words, zero before the first launch) is the
+// work counter and the exit counter, reset by the last wave to finish.
+hipError_t launch_u8_batched(const U8Job *jobs, const int32_t *wt_prefix, int32_t count,
+                             uint32_t *queue, int border_valid, bool aligned, const U8Shape &s,
+                             int grid, hipStream_t stream);
+
+// Number of workgroups of the persistent kernel that fit on the device at
+// once for shape `s` (occupancy x CUs), or 0 on error.
+int u8_persistent_grid(const U8Shape &s, int border_valid, bool aligned);
+
+hipError_t launch_round_mag(const int32_t *s2, uint8_t *out, int64_t n, hipStream_t stream);
+
+// fp32 path (pointers and strides as in the public header).
+struct F32Args {
+    const float *src;
+    int64_t src_pitch, src_bstride;       // bytes
+    float *out;
+    int64_t out_pitch, out_bstride;       // bytes
+    const float *grad;                    // bwd only
+    int64_t g_pitch, g_bstride;           // bytes
+    int32_t B, W, H, Wo, Ho;
+    int32_t off;                          // 0 replicate, 2 valid
+};
+
+hipError_t launch_f32_fwd(const F32Args &a, hipStream_t stream);
+hipError_t launch_f32_bwd(const F32Args &a, hipStream_t stream);
+
+}  // namespace s4x5

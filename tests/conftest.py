@@ -18,3 +18,21 @@ def oracle_mod():
     import oracle
     oracle.build()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def sobel_lib():
+    """The built HIP library's binding (built here first if it is missing)."""
+    from paper_2305_00515_amd import build as b
+    if not b.LIB.exists():
+        b.build()
+    from paper_2305_00515_amd import api
+    return api
+
+
+@pytest.fixture(scope="session")
+def gpu(sobel_lib):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")

@@ -1,0 +1,119 @@
+"""GPU parity of the batched persistent path (plans, hipGraph, autotune)."""
+import numpy as np
+import pytest
+
+from paper_2305_00515_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def upload(img, dev, pitch):
+    h, w = img.shape
+    flat = torch.zeros(((h - 1) * pitch + w,), dtype=torch.uint8, device=dev)
+    v = flat.as_strided((h, w), (pitch, 1))
+    v.copy_(torch.from_numpy(np.ascontiguousarray(img)))
+    return v
+
+
+def make_batch(sizes, dev, seed0=1000, border=0, pitch_fn=lambda w: synth.round_up(w, 256)):
+    imgs = [synth.rect_image(h, w, seed0 + i) for i, (h, w) in enumerate(sizes)]
+    srcs = [upload(m, dev, pitch_fn(m.shape[1])) for m in imgs]
+    mags = []
+    for (h, w) in sizes:
+        ho, wo = (h, w) if border == 0 else (h - 4, w - 4)
+        mags.append(torch.full((ho, wo), 0x5A, dtype=torch.uint8, device=dev))
+    return imgs, srcs, mags
+
+
+def check_all(oracle_mod, imgs, mags, border=0):
+    torch.cuda.synchronize()
+    for i, (img, m) in enumerate(zip(imgs, mags)):
+        om, _ = oracle_mod.sobel_u8(img, border, want_dir=False)
+        got = m.cpu().numpy()
+        assert np.array_equal(got, om), "image %d %s differs in %d pixels" % (i, img.shape, int((got != om).sum()))
+
+
+SMALL = [(1, 1), (2, 300), (300, 2), (5, 5), (17, 250), (128, 128), (64, 1000), (333, 257),
+         (700, 129), (1000, 1000), (7, 4096), (129, 555)]
+
+
+@pytest.mark.parametrize("border", [0, 1])
+def test_small_mixed_batch(oracle_mod, sobel_lib, gpu, border):
+    sizes = [s for s in SMALL if border == 0 or min(s) >= 5]
+    imgs, srcs, mags = make_batch(sizes, gpu, border=border)
+    plan = sobel_lib.Plan(srcs, mags, border)
+    plan.launch()
+    check_all(oracle_mod, imgs, mags, border)
+    # replays reset their queue: clear outputs and launch three more times
+    for _ in range(3):
+        for m in mags:
+            m.fill_(0)
+        plan.launch()
+        check_all(oracle_mod, imgs, mags, border)
+    plan.close()
+
+
+def test_one_shot_and_cache(oracle_mod, sobel_lib, gpu):
+    imgs, srcs, mags = make_batch(SMALL, gpu)
+    sobel_lib.sobel4x5_batched(srcs, mags)
+    check_all(oracle_mod, imgs, mags)
+    for m in mags:
+        m.fill_(0)
+    sobel_lib.sobel4x5_batched(srcs, mags)          # cached plan
+    check_all(oracle_mod, imgs, mags)
+
+
+def test_batch_of_one_and_duplicates(oracle_mod, sobel_lib, gpu):
+    imgs, srcs, mags = make_batch([(400, 900)], gpu)
+    sobel_lib.Plan(srcs, mags).launch()
+    check_all(oracle_mod, imgs, mags)
+    # the same source image twice, two outputs
+    m2 = [torch.zeros_like(mags[0]), torch.zeros_like(mags[0])]
+    sobel_lib.Plan([srcs[0], srcs[0]], m2).launch()
+    check_all(oracle_mod, imgs * 2, m2)
+
+
+def test_unaligned_images(oracle_mod, sobel_lib, gpu):
+    sizes = [(50, 61), (33, 200), (80, 1001)]
+    imgs, srcs, mags = make_batch(sizes, gpu, pitch_fn=lambda w: w + 1)
+    sobel_lib.Plan(srcs, mags, graph=False).launch()
+    check_all(oracle_mod, imgs, mags)
+
+
+def test_autotune_is_bit_exact(oracle_mod, sobel_lib, gpu, tmp_path, monkeypatch):
+    monkeypatch.setenv("SOBEL4X5_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    sizes = synth.batch_sizes(16, 5, 128, 1500)
+    imgs, srcs, mags = make_batch(sizes, gpu)
+    plan = sobel_lib.Plan(srcs, mags, autotune=True)
+    info = plan.info()
+    assert info["px_per_lane"] in (8, 16) and info["rows_per_tile"] >= 8
+    for m in mags:
+        m.fill_(0)
+    plan.launch()
+    check_all(oracle_mod, imgs, mags)
+    assert (tmp_path / "tune.txt").exists()
+    plan2 = sobel_lib.Plan(srcs, mags, autotune=True)      # served from the cache file
+    assert plan2.info()["rows_per_tile"] == info["rows_per_tile"]
+
+
+def test_config3_full_batch_vs_single_image_path(oracle_mod, sobel_lib, gpu):
+    """256 images, sides uniform in [128, 4096]: one persistent graph launch
+    equals the single-image kernel on every image, bit for bit, and sampled
+    pixels of every image equal the oracle."""
+    sizes = synth.batch_sizes(256, 77)
+    imgs = [synth.rect_image(h, w, 1000 + i) for i, (h, w) in enumerate(sizes)]
+    srcs = [upload(m, gpu, synth.round_up(m.shape[1], 256)) for m in imgs]
+    mags = [torch.zeros((h, w), dtype=torch.uint8, device=gpu) for (h, w) in sizes]
+    plan = sobel_lib.Plan(srcs, mags)
+    plan.launch()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    for i, (img, s, m) in enumerate(zip(imgs, srcs, mags)):
+        ref = sobel_lib.sobel4x5_u8(s)[0]
+        assert torch.equal(ref, m), "image %d" % i
+        h, w = img.shape
+        ys = np.concatenate([rng.integers(0, h, 300), [0, h - 1, 0, h - 1]])
+        xs = np.concatenate([rng.integers(0, w, 300), [0, 0, w - 1, w - 1]])
+        om, _ = oracle_mod.sobel_u8_points(img, ys, xs)
+        assert np.array_equal(m.cpu().numpy()[ys, xs], om), "image %d" % i

@@ -105,3 +105,19 @@ def test_f64_backward_central_differences(oracle_mod):
         h0 = 1e-4
         rich = (4 * fd(h0 / 2) - fd(h0)) / 3
         assert abs(rich - dx[0, py, px]) <= 1e-7 * max(1.0, abs(dx[0, py, px])), (py, px)
+
+
+def test_error_scales_bound_the_results(oracle_mod):
+    """The tolerance scales dominate the quantities they scale."""
+    rng = np.random.default_rng(4)
+    x = rng.random((2, 14, 17))
+    M, D = oracle_mod.sobel_f64_fwd(x, want_dir=True)
+    sf = oracle_mod.sobel_f64_fwd_scale(x)
+    assert np.all(np.abs(D).max(axis=1) <= sf + 1e-12)
+    g = rng.standard_normal(M.shape)
+    dx = oracle_mod.sobel_f64_bwd(x, g)
+    A = oracle_mod.sobel_f64_bwd_scale(x, g)
+    assert np.all(np.abs(dx) <= A + 1e-12)
+    assert np.all(A >= 0)
+    # a constant image has no terms at all
+    assert not oracle_mod.sobel_f64_bwd_scale(np.full((1, 8, 8), 0.7), np.ones((1, 8, 8))).any()
