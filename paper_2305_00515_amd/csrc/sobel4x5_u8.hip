@@ -408,12 +408,17 @@ __device__ void wave_tile(const U8Job &J, int wt, int TH)
         row_filters<NP>(R, hr, hs);
     };
 
-    // prologue: rows t = 0..3 (+ prefetch up to 3 + kPD)
+    // prologue: rows t = 0..4 in flight, rows 0..3 processed (which frees
+    // their slots), then rows 5 .. 3 + kPD.  Row t always lives in raw[t % 5].
+    static_assert(kPD >= 1 && kPD <= 4, "prefetch distance must fit the 5-slot ring");
 #pragma unroll
-    for (int t = 0; t < 4 + kPD; ++t)
-        if (t <= niter + 3) fetch(t, raw[t % 5]);
+    for (int t = 0; t < 5; ++t)
+        if (t <= niter + 3) fetch(t, raw[t]);
 #pragma unroll
     for (int t = 0; t < 4; ++t) process(t, raw[t], Rr[t], HR[t], HS[t]);
+#pragma unroll
+    for (int t = 5; t < 4 + kPD; ++t)
+        if (t <= niter + 3) fetch(t, raw[t % 5]);
 #pragma unroll
     for (int c = 0; c < NP + 4; ++c) {
         A2r[1][c] = Rr[2][c] - Rr[0][c];
