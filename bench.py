@@ -35,7 +35,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
-    p.add_argument("--only", choices=["u8", "batched", "f32", "sweep"], default=None)
+    p.add_argument("--only", choices=["u8", "batched", "f32", "sweep", "copy"], default=None)
     p.add_argument("--no-cpu-baseline", action="store_true")
     return p.parse_args()
 
@@ -177,6 +177,20 @@ def bench_f32(torch, api, synth, dev, steps, warmup):
     return res
 
 
+def bench_copy(torch, api, dev, steps):
+    """Achievable streaming bandwidth: a plain 128-bit copy of 1 GiB (2 GiB moved)."""
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device=dev)
+    b = torch.empty(n, dtype=torch.uint8, device=dev)
+    a.fill_(7)
+    k = max(3, steps // 20)
+    ms = time_launches(torch, lambda i: api.debug_copy(a, b) if i % 2 == 0 else api.debug_copy(b, a), k, 2)
+    gbs = 2 * n / (ms * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_moved": 2 * n, "ms": round(ms, 4), "GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def cpu_baseline(img):
     """The CPU oracle (as it stands) on the same 8192x8192 image, all cores."""
     import oracle
@@ -240,6 +254,9 @@ def main():
                          "kernel": "k_u8_single<16,0,aligned,mag-only>",
                          "alg_bytes_per_launch": r["alg_bytes"]},
         })
+    if only in (None, "copy"):
+        log("copy ceiling")
+        line["copy_ceiling"] = bench_copy(torch, api, dev, args.steps)
     if only in (None, "sweep"):
         log("sweep")
         line["sweep"] = bench_sweep(torch, api, synth, dev, args.steps, args.warmup)

@@ -189,10 +189,18 @@ int sobel4x5_validate_f32(const float *src, int32_t batch, int32_t width, int32_
 
 /*
  * Diagnostic: the library's uint8 rounding of the magnitude, applied to n
- * given values of 2*S (S = sum of the four squared responses, so 2*S is
- * even).  out[i] = min(255, round(sqrt(s2[i] / 2))).  Device pointers.
+ * given values of S (the sum of the four squared responses, 0 <= S < 2^31).
+ * out[i] = min(255, round(sqrt(S[i]))).  Device pointers; n >= 0.
  */
-int sobel4x5_debug_round_mag(const int32_t *s2, uint8_t *out, int64_t n, void *stream);
+int sobel4x5_debug_round_mag(const int32_t *S, uint8_t *out, int64_t n, void *stream);
+
+/*
+ * Diagnostic: plain device-to-device copy of nbytes (a multiple of 16;
+ * 16-byte aligned device pointers), the same 128-bit streaming access the
+ * stencil uses.  It is the measured reference for the achievable HBM
+ * bandwidth and the calibration of memory-traffic counters.
+ */
+int sobel4x5_debug_copy(const void *src, void *dst, int64_t nbytes, void *stream);
 
 const char *sobel4x5_status_string(int status);
 const char *sobel4x5_last_error(void);

@@ -9,12 +9,14 @@ be loaded raises, and there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes
+import os
 from pathlib import Path
 
 import torch
 
 _PKG = Path(__file__).resolve().parent
-LIB_PATH = _PKG / "libsobel4x5.so"
+# SOBEL4X5_LIBRARY may name another build of the same library (tuning runs)
+LIB_PATH = Path(os.environ.get("SOBEL4X5_LIBRARY") or (_PKG / "libsobel4x5.so"))
 
 BORDER_REPLICATE = 0
 BORDER_VALID = 1
@@ -64,6 +66,7 @@ def _load() -> ctypes.CDLL:
         "sobel4x5_f32_bwd": [P, I64, I64, P, I64, I64, I32, I32, I32, I32, P, I64, I64, P],
         "sobel4x5_validate_f32": [P, I32, I32, I32, I64, I64, I32, P, I64, I64],
         "sobel4x5_debug_round_mag": [P, P, I64, P],
+        "sobel4x5_debug_copy": [P, P, I64, P],
         "sobel4x5_status_string": [ctypes.c_int],
         "sobel4x5_last_error": [],
         "sobel4x5_version": [],
@@ -265,14 +268,24 @@ def sobel4x5_f32_bwd(x: torch.Tensor, grad_mag: torch.Tensor, border: int = BORD
     return out if x.dim() == 3 else out.view(h, w)
 
 
-def debug_round_mag(s2: torch.Tensor) -> torch.Tensor:
-    """The library's uint8 rounding applied to values of 2*S (int32 tensor)."""
-    _need_cuda(s2, torch.int32, "s2")
-    s2 = s2.contiguous()
-    out = torch.empty(s2.shape, dtype=torch.uint8, device=s2.device)
-    _check(lib.sobel4x5_debug_round_mag(s2.data_ptr(), out.data_ptr(), s2.numel(), _stream(s2)),
+def debug_round_mag(S: torch.Tensor) -> torch.Tensor:
+    """The library's uint8 rounding min(255, round(sqrt(S))) of int32 values S."""
+    _need_cuda(S, torch.int32, "S")
+    S = S.contiguous()
+    out = torch.empty(S.shape, dtype=torch.uint8, device=S.device)
+    _check(lib.sobel4x5_debug_round_mag(S.data_ptr(), out.data_ptr(), S.numel(), _stream(S)),
            "sobel4x5_debug_round_mag")
     return out
+
+
+def debug_copy(src: torch.Tensor, dst: torch.Tensor) -> None:
+    """Plain 128-bit streaming copy of src into dst (same byte size)."""
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("contiguous GPU tensors required")
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n:
+        raise ValueError("size mismatch")
+    _check(lib.sobel4x5_debug_copy(src.data_ptr(), dst.data_ptr(), n, _stream(src)), "sobel4x5_debug_copy")
 
 
 def status_string(code: int) -> str:

@@ -35,10 +35,16 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> Path:
-    """Compile every source into libsobel4x5.so (always recompiles)."""
-    tmp = LIB.with_suffix(".so.tmp%d" % os.getpid())
-    cmd = [hipcc()] + FLAGS + ["-o", str(tmp)] + [str(CSRC / s) for s in SOURCES]
+def build(verbose: bool = False, out: Path | None = None, defines=()) -> Path:
+    """Compile every source into libsobel4x5.so (always recompiles).
+
+    ``out`` and ``defines`` (NAME=VALUE strings) build a variant elsewhere,
+    for tuning experiments; the package always loads LIB unless
+    SOBEL4X5_LIBRARY names another build.
+    """
+    out = Path(out) if out else LIB
+    tmp = out.with_suffix(".so.tmp%d" % os.getpid())
+    cmd = [hipcc()] + FLAGS + ["-D" + d for d in defines] + ["-o", str(tmp)] + [str(CSRC / s) for s in SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -47,10 +53,15 @@ def build(verbose: bool = False) -> Path:
         raise RuntimeError("hipcc failed building libsobel4x5.so")
     if verbose and res.stderr.strip():
         sys.stderr.write(res.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    build(verbose="--verbose" in sys.argv)
-    print(LIB)
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--out", default=None)
+    ap.add_argument("-D", dest="defines", action="append", default=[])
+    a = ap.parse_args()
+    print(build(verbose=a.verbose, out=a.out, defines=a.defines))

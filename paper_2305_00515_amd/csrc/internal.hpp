@@ -24,7 +24,8 @@ struct U8Job {
     int32_t ntx;           // tile columns (tile width = 16 lanes * px_per_lane)
     int32_t nty4;          // ceil(tile rows / 4): a wave takes 4 stacked tiles
     int32_t nty;           // tile rows
-    int32_t nwt;           // wave tiles = ntx * nty4
+    int32_t nwt;           // wave tiles, 4 tiles stacked per wave = ntx * nty4
+    int32_t nwt_h;         // wave tiles, 4 tiles side by side = ceil(ntx / 4) * nty
     int32_t mag_vec;       // mag rows 16-byte aligned: vector stores allowed
     int32_t dir_vec;       // dir rows 16-byte aligned
 };
@@ -32,9 +33,10 @@ struct U8Job {
 // Tile shape.  A 16-lane group owns a tile of (16 * ppl) columns x th rows;
 // a wave owns 4 vertically stacked tiles.
 struct U8Shape {
-    int ppl;   // pixels per lane: 8 or 16
-    int th;    // rows per tile
-    int wpg;   // waves per workgroup: 2, 4 or 8
+    int ppl;        // pixels per lane: 8 or 16
+    int th;         // rows per tile (batched kernel)
+    int wpg;        // waves per workgroup (4)
+    int waves = 0;  // single-image kernel: waves to launch (0 = all resident waves)
 };
 
 // True when the fast (vector-load) kernel may read this image: 16-byte
@@ -44,7 +46,8 @@ bool u8_rows_aligned(const U8Job &j);
 // Fills the tiling fields of `j` for shape `s`.
 void u8_tile(U8Job &j, const U8Shape &s);
 
-// Single image: one launch, one wave per wave-tile.
+// Single image: one launch; every resident wave takes an equal row range of
+// one strip of four tiles.
 hipError_t launch_u8_single(const U8Job &j, int border_valid, const U8Shape &s,
                             hipStream_t stream);
 
@@ -61,7 +64,8 @@ hipError_t launch_u8_batched(const U8Job *jobs, const int32_t *wt_prefix, int32_
 // once for shape `s` (occupancy x CUs), or 0 on error.
 int u8_persistent_grid(const U8Shape &s, int border_valid, bool aligned);
 
-hipError_t launch_round_mag(const int32_t *s2, uint8_t *out, int64_t n, hipStream_t stream);
+hipError_t launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t stream);
+hipError_t launch_round_mag(const int32_t *S, uint8_t *out, int64_t n, hipStream_t stream);
 
 // fp32 path (pointers and strides as in the public header).
 struct F32Args {

@@ -144,25 +144,29 @@ U8Job make_job(const uint8_t *src, int32_t W, int32_t H, int64_t pitch, int32_t 
     return j;
 }
 
-// Default shape for one image: 16 pixels per lane when the image is wide
-// enough to fill a 256-column tile, then the tallest tile that still gives
-// at least ~8 wave-tiles per compute unit.
-U8Shape default_shape(int32_t Wo, int32_t Ho)
+int env_int(const char *name, int dflt)
 {
+    const char *v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    char *end = nullptr;
+    const long x = std::strtol(v, &end, 10);
+    return (end && *end == 0 && x >= 0 && x < (1 << 30)) ? (int)x : dflt;
+}
+
+// Shape for one image: 16 pixels per lane when a strip of four 256-column
+// tiles is mostly inside the image, else 8; directional outputs use 8 (their
+// kernel keeps more values live).  SOBEL4X5_U8_PPL (8 or 16) and
+// SOBEL4X5_U8_WAVES (waves to launch) override the choice for tuning runs.
+U8Shape default_shape(int32_t Wo, int32_t Ho, int32_t dir_type)
+{
+    (void)Ho;
     U8Shape s;
-    s.ppl = Wo >= 192 ? 16 : 8;
+    s.ppl = (Wo >= 768 && dir_type == SOBEL4X5_DIR_NONE) ? 16 : 8;
+    const int ppl = env_int("SOBEL4X5_U8_PPL", 0);
+    if (ppl == 8 || ppl == 16) s.ppl = ppl;
+    s.th = 32;
     s.wpg = 4;
-    const int64_t tw = 16 * s.ppl;
-    const int64_t ntx = (Wo + tw - 1) / tw;
-    const int th_opts[] = {64, 32, 16, 8};
-    s.th = 8;
-    for (int th : th_opts) {
-        const int64_t nty4 = ((Ho + th - 1) / th + 3) / 4;
-        if (ntx * nty4 >= 2048) {
-            s.th = th;
-            break;
-        }
-    }
+    s.waves = env_int("SOBEL4X5_U8_WAVES", 0);
     return s;
 }
 
@@ -546,7 +550,7 @@ int sobel4x5_u8(const uint8_t *src, int32_t width, int32_t height, int64_t src_p
     if (int rc = validate_u8(src, width, height, src_pitch, border, out, &Wo, &Ho)) return rc;
     U8Job j = make_job(src, width, height, src_pitch, Wo, Ho, out->mag, out->mag_pitch,
                        out->dir_type ? out->dir : nullptr, out->dir_pitch, out->dir_type);
-    const U8Shape s = default_shape(Wo, Ho);
+    const U8Shape s = default_shape(Wo, Ho, out->dir_type);
     u8_tile(j, s);
     hipError_t e = launch_u8_single(j, border == SOBEL4X5_BORDER_VALID, s, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_u8 launch");
@@ -718,10 +722,19 @@ int sobel4x5_f32_bwd(const float *src, int64_t src_pitch, int64_t src_bstride, c
     return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_f32_bwd launch");
 }
 
-int sobel4x5_debug_round_mag(const int32_t *s2, uint8_t *out, int64_t n, void *stream)
+int sobel4x5_debug_copy(const void *src, void *dst, int64_t nbytes, void *stream)
 {
-    if (n < 0 || (n > 0 && (!s2 || !out))) return fail(SOBEL4X5_EINVAL, "bad arguments");
-    hipError_t e = launch_round_mag(s2, out, n, static_cast<hipStream_t>(stream));
+    if (nbytes < 0 || (nbytes % 16) || (nbytes > 0 && (!src || !dst)) ||
+        ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15u))
+        return fail(SOBEL4X5_EINVAL, "copy needs 16-byte aligned pointers and a multiple of 16 bytes");
+    hipError_t e = launch_copy16(src, dst, nbytes / 16, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_debug_copy launch");
+}
+
+int sobel4x5_debug_round_mag(const int32_t *S, uint8_t *out, int64_t n, void *stream)
+{
+    if (n < 0 || (n > 0 && (!S || !out))) return fail(SOBEL4X5_EINVAL, "bad arguments");
+    hipError_t e = launch_round_mag(S, out, n, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_debug_round_mag launch");
 }
 

@@ -38,7 +38,11 @@
 
 #include "internal.hpp"
 
+#include <algorithm>
+#include <mutex>
 #include <type_traits>
+#include <utility>
+#include <vector>
 
 namespace s4x5 {
 namespace {
@@ -51,7 +55,7 @@ __device__ __forceinline__ u32 U2(v2s v) { return __builtin_bit_cast(u32, v); }
 __device__ __forceinline__ u32 perm(u32 hi, u32 lo, u32 sel) { return __builtin_amdgcn_perm(hi, lo, sel); }
 
 constexpr u32 kZeroByte = 0x0c;   // v_perm selector that yields 0x00
-constexpr int kPD = 2;            // rows loaded ahead of use
+constexpr int kPD = 4;            // rows loaded ahead of use
 
 // v_perm selector: byte0 <- byte `lob` of the low source, byte2 <- byte
 // `hib` of the high source, bytes 1 and 3 <- 0: two zero-extended pixels.
@@ -60,16 +64,35 @@ constexpr u32 pair_sel(int lob, int hib)
     return (kZeroByte << 24) | ((4u + (u32)hib) << 16) | (kZeroByte << 8) | (u32)lob;
 }
 
-// Round-to-nearest of sqrt(s2 / 2), saturated to 255.  s2 = 2S is even, so
-// s2 * 0.5f is S (exactly below 2^24; monotone above, where the result
-// saturates anyway).  v_sqrt_f32 is within 1 ulp and an integer S is never
-// closer than 4.9e-4 to a half-integer square root, so the rounding is exact.
-__device__ __forceinline__ u32 round_mag(int s2)
+// Round-to-nearest of sqrt(S), saturated to 255.  (float)S is exact below
+// 2^24 and monotone above, where the result saturates anyway; v_sqrt_f32 is
+// within 1 ulp, and an integer S is never closer than 4.9e-4 to a
+// half-integer square root, so rounding the float result is exact.
+__device__ __forceinline__ float mag_f(int S) { return __builtin_amdgcn_sqrtf((float)S); }
+
+__device__ __forceinline__ u32 round_mag(int S)
 {
-    float f = (float)s2 * 0.5f;
-    float r = __builtin_amdgcn_sqrtf(f);
-    u32 m = (u32)(r + 0.5f);
-    return m < 255u ? m : 255u;
+    // v_cvt_pk_u8_f32: round to nearest, saturate to [0, 255] (no ties occur)
+    return __builtin_amdgcn_cvt_pk_u8_f32(mag_f(S), 0, 0u);
+}
+
+// a.lo^2 + a.hi^2 of two int16 halves (VOP3P dot with a zero accumulator)
+__device__ __forceinline__ int dot2_sq(u32 a)
+{
+    int r;
+    asm("v_dot2_i32_i16 %0, %1, %1, 0" : "=v"(r) : "v"(a));
+    return r;
+}
+
+// A packed (c, c) constant the optimiser cannot see through, so that
+// products with it stay single v_pk_mad_u16 instructions instead of being
+// strength-reduced into shift + add pairs.
+template <int C>
+__device__ __forceinline__ v2s kconst()
+{
+    u32 r;
+    asm("s_mov_b32 %0, %1" : "=s"(r) : "i"((int)(((unsigned)C & 0xffffu) | ((unsigned)C << 16))));
+    return S2(r);
 }
 
 // The 20-byte window of one lane for one row: the lane's own ppl bytes
@@ -121,43 +144,49 @@ __device__ __forceinline__ void row_filters(const v2s (&R)[NP + 4], v2s (&hr)[NP
         v2s s = R[j + 3] - R[j + 1];
         v2s e = R[j + 4] - R[j];
         hs[j] = s;
-        hr[j] = e + s + s;
+        hr[j] = s * kconst<2>() + e;
     }
 }
 
-// Gy and Gd+ at one output row (columns first).  vr = v_r and a2 = v_s of
-// the output row's centre, both for NP + 4 columns.
+// Gy and Hp = Gd+/2 at one output row (columns first).  vr = v_r and a2 =
+// v_s of the output row's centre, both for NP + 4 columns.  Every entry of
+// K_d+ and K_d- is even, so Gd+/2 and Gd-/2 are integers and take one
+// multiply-add less than Gd+- itself.
 template <int NP>
 __device__ __forceinline__ void responses_y(const v2s (&vr)[NP + 4], const v2s (&a2)[NP + 4],
-                                            v2s (&Gy)[NP], v2s (&Gp)[NP])
+                                            v2s (&Gy)[NP], v2s (&Hp)[NP])
 {
+    const v2s k3 = kconst<3>(), k4 = kconst<4>(), k6 = kconst<6>(), km5 = kconst<-5>();
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         const int c = j + 2;
         v2s p4 = vr[c - 2] + vr[c + 2];
         v2s p2 = vr[c - 1] + vr[c + 1];
-        Gy[j] = p4 + p2 * (short)4 + vr[c] * (short)6;
-        Gp[j] = (p4 + p2) * (short)6 + vr[c] * (short)2 - (a2[c - 2] + a2[c + 2]) * (short)10 +
-                a2[c] * (short)12;
+        Gy[j] = vr[c] * k6 + (p2 * k4 + p4);
+        v2s t = (p4 + p2) * k3 + vr[c];
+        t = (a2[c - 2] + a2[c + 2]) * km5 + t;
+        Hp[j] = a2[c] * k6 + t;
     }
 }
 
-// Gx and Gd- at one output row (rows first) from the row filters of the
-// five window rows.
+// Gx and Hm = Gd-/2 at one output row (rows first) from the row filters of
+// the five window rows.
 template <int NP>
 __device__ __forceinline__ void responses_x(const v2s (&hr0)[NP], const v2s (&hr1)[NP],
                                             const v2s (&hr2)[NP], const v2s (&hr3)[NP],
                                             const v2s (&hr4)[NP], const v2s (&hs0)[NP],
                                             const v2s (&hs2)[NP], const v2s (&hs4)[NP],
-                                            v2s (&Gx)[NP], v2s (&Gm)[NP])
+                                            v2s (&Gx)[NP], v2s (&Hm)[NP])
 {
+    const v2s k3 = kconst<3>(), k4 = kconst<4>(), k6 = kconst<6>(), km5 = kconst<-5>();
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         v2s x1 = hr0[j] + hr4[j];
         v2s x2 = hr1[j] + hr3[j];
-        Gx[j] = x1 + x2 * (short)4 + hr2[j] * (short)6;
-        Gm[j] = (x1 + x2) * (short)6 + hr2[j] * (short)2 - (hs0[j] + hs4[j]) * (short)10 +
-                hs2[j] * (short)12;
+        Gx[j] = hr2[j] * k6 + (x2 * k4 + x1);
+        v2s t = (x1 + x2) * k3 + hr2[j];
+        t = (hs0[j] + hs4[j]) * km5 + t;
+        Hm[j] = hs2[j] * k6 + t;
     }
 }
 
@@ -191,7 +220,7 @@ struct RawRow {
 
 // Issue the loads of one row (fast path: 16-byte aligned rows).
 template <int PPL>
-__device__ __forceinline__ void load_row(RawRow<PPL> &r, const uint8_t *rowp, int ldx, int hx)
+__device__ __forceinline__ void load_row(RawRow<PPL> &r, const uint8_t *rowp, unsigned ldx, unsigned hx)
 {
     if constexpr (PPL == 16) {
         uint4 v = *reinterpret_cast<const uint4 *>(rowp + ldx);
@@ -205,7 +234,7 @@ __device__ __forceinline__ void load_row(RawRow<PPL> &r, const uint8_t *rowp, in
 
 // Turn a loaded row into the lane's window: border fix-ups, then DPP halo.
 template <int PPL, int OFF>
-__device__ __forceinline__ Win<PPL> finish_row(RawRow<PPL> r, int lane16, int xo, int W,
+__device__ __forceinline__ Win<PPL> finish_row(RawRow<PPL> &r, int lane16, int xo, int W,
                                                bool fix_right, bool fix_left)
 {
     constexpr int ND = PPL / 4;
@@ -255,37 +284,40 @@ __device__ __forceinline__ Win<PPL> load_row_bytes(const uint8_t *rowp, int xo, 
     return w;
 }
 
-// Stores of one output row for one lane.
-template <int NP, bool DIR>
+// Stores of one output row for one lane, from Gx, Gy, Hp = Gd+/2 and
+// Hm = Gd-/2.
+template <int NP, bool DIR, bool FAST>
 __device__ __forceinline__ void store_row(const U8Job &J, int yo, int xo, bool row_ok,
-                                          const v2s (&Gx)[NP], const v2s (&Gp)[NP],
-                                          const v2s (&Gy)[NP], const v2s (&Gm)[NP])
+                                          const v2s (&Gx)[NP], const v2s (&Hp)[NP],
+                                          const v2s (&Gy)[NP], const v2s (&Hm)[NP])
 {
     constexpr int PPL = 2 * NP;
-    if (!row_ok) return;
+    if (!FAST && !row_ok) return;
     const int nvalid = J.Wo - xo;          // pixels of this lane inside the image
-    if (nvalid <= 0) return;
-    const bool full = nvalid >= PPL;
-    if (J.mag) {
+    if (!FAST && nvalid <= 0) return;
+    const bool full = FAST || nvalid >= PPL;
+    if (DIR ? J.mag != nullptr : true) {
         u32 out[PPL / 4];
 #pragma unroll
-        for (int m = 0; m < PPL / 4; ++m) out[m] = 0;
-#pragma unroll
         for (int j = 0; j < NP; ++j) {
+            // S = Gx^2 + Gy^2 + Gd^2 + Gdt^2 = Gx^2 + Gy^2 + 2 (Hp^2 + Hm^2):
+            // byte permutes pair (Gx, Gy) and (Hp, Hm) of one pixel, v_dot2
+            // squares and sums each pair.
             const u32 xyl = perm(U2(Gy[j]), U2(Gx[j]), 0x05040100u);
             const u32 xyh = perm(U2(Gy[j]), U2(Gx[j]), 0x07060302u);
-            const u32 ddl = perm(U2(Gm[j]), U2(Gp[j]), 0x05040100u);
-            const u32 ddh = perm(U2(Gm[j]), U2(Gp[j]), 0x07060302u);
-            const int tl = __builtin_amdgcn_sdot2(S2(xyl), S2(xyl), 0, false);
-            const int th = __builtin_amdgcn_sdot2(S2(xyh), S2(xyh), 0, false);
-            const int sl = __builtin_amdgcn_sdot2(S2(ddl), S2(ddl), tl * 2, false);
-            const int sh = __builtin_amdgcn_sdot2(S2(ddh), S2(ddh), th * 2, false);
+            const u32 hhl = perm(U2(Hm[j]), U2(Hp[j]), 0x05040100u);
+            const u32 hhh = perm(U2(Hm[j]), U2(Hp[j]), 0x07060302u);
+            const int sl = 2 * dot2_sq(hhl) + dot2_sq(xyl);
+            const int sh = 2 * dot2_sq(hhh) + dot2_sq(xyh);
             const int ql = j, qh = j + NP;   // pixel indices inside the lane
-            out[ql >> 2] |= round_mag(sl) << (8 * (ql & 3));
-            out[qh >> 2] |= round_mag(sh) << (8 * (qh & 3));
+            const float fl = mag_f(sl), fh = mag_f(sh);
+            // the first byte written into a word starts from any value: all
+            // four bytes of every word are overwritten
+            out[ql >> 2] = __builtin_amdgcn_cvt_pk_u8_f32(fl, ql & 3, (ql & 3) ? out[ql >> 2] : __builtin_bit_cast(u32, fl));
+            out[qh >> 2] = __builtin_amdgcn_cvt_pk_u8_f32(fh, qh & 3, (qh & 3) ? out[qh >> 2] : __builtin_bit_cast(u32, fh));
         }
-        uint8_t *p = J.mag + (int64_t)yo * J.mag_pitch + xo;
-        if (full && J.mag_vec) {
+        uint8_t *p = (J.mag + (int64_t)yo * J.mag_pitch) + (unsigned)xo;
+        if (FAST || (full && J.mag_vec)) {
             if constexpr (PPL == 16)
                 *reinterpret_cast<uint4 *>(p) = make_uint4(out[0], out[1], out[2], out[3]);
             else
@@ -303,10 +335,8 @@ __device__ __forceinline__ void store_row(const U8Job &J, int yo, int xo, bool r
         for (int j = 0; j < NP; ++j) {
             P[0][j] = Gx[j];
             P[2][j] = Gy[j];
-            v2s sum = Gp[j] + Gm[j];
-            v2s dif = Gp[j] - Gm[j];
-            P[1][j] = sum >> (short)1;            // exact: Gd+ + Gd- = 2 Gd
-            P[3][j] = dif >> (short)1;
+            P[1][j] = Hp[j] + Hm[j];              // Gd  = (Gd+ + Gd-)/2 = Hp + Hm
+            P[3][j] = Hp[j] - Hm[j];              // Gdt = (Gd+ - Gd-)/2 = Hp - Hm
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -320,7 +350,7 @@ __device__ __forceinline__ void store_row(const U8Job &J, int yo, int xo, bool r
                                   : perm(U2(P[k][a - NP + 1]), U2(P[k][a - NP]), 0x07060302u);
                 }
                 int16_t *p = reinterpret_cast<int16_t *>(base) + xo;
-                if (full && J.dir_vec) {
+                if (FAST || (full && J.dir_vec)) {
 #pragma unroll
                     for (int m = 0; m < NP; m += 4)
                         *reinterpret_cast<uint4 *>(p + 2 * m) = make_uint4(o[m], o[m + 1], o[m + 2], o[m + 3]);
@@ -337,7 +367,7 @@ __device__ __forceinline__ void store_row(const U8Job &J, int yo, int xo, bool r
                     o[j + NP] = P[k][j].y;
                 }
                 int32_t *p = reinterpret_cast<int32_t *>(base) + xo;
-                if (full && J.dir_vec) {
+                if (FAST || (full && J.dir_vec)) {
 #pragma unroll
                     for (int q = 0; q < PPL; q += 4)
                         *reinterpret_cast<int4 *>(p + q) = make_int4(o[q], o[q + 1], o[q + 2], o[q + 3]);
@@ -353,50 +383,56 @@ __device__ __forceinline__ void store_row(const U8Job &J, int yo, int xo, bool r
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// One wave-tile: 4 tiles stacked vertically in one tile column, one per
-// 16-lane group.  `wt` is the wave-tile index inside image J.
-template <int PPL, int OFF, bool ALIGNED, bool DIR>
-__device__ void wave_tile(const U8Job &J, int wt, int TH)
+// What one wave sweeps: per lane the output column xo of its first pixel,
+// per 16-lane group the first output row yo0 and its row count nrow (0 for
+// an idle group); the wave walks niter rows (the largest nrow).  fix_right /
+// fix_left: the wave touches the right / left image border (replicate).
+struct Sweep {
+    int xo, yo0, nrow, niter;
+    bool fix_right, fix_left;
+};
+
+// Sweep the wave's tiles top to bottom.  FAST: an interior wave (no border
+// fix-ups, every group active for all niter rows, aligned rows and outputs):
+// the loop body has no branches, so the compiler can schedule across steps.
+template <int PPL, int OFF, bool ALIGNED, bool DIR, bool FAST>
+__device__ void sweep(const U8Job &J, const Sweep &g)
 {
     constexpr int NP = PPL / 2;
-    constexpr int TW = 16 * PPL;
-    const int lane = threadIdx.x & 63;
-    const int lane16 = lane & 15;
-    const int grp = lane >> 4;
-    const int tx = wt % J.ntx;                       // wave-uniform
-    const int ty = (wt / J.ntx) * 4 + grp;           // per group
-    const int xo = tx * TW + lane16 * PPL;
-    const int yo0 = ty * TH;
-    const int nrow = ty < J.nty ? min(TH, J.Ho - yo0) : 0;
-    int niter = max(max(__builtin_amdgcn_readlane(nrow, 0), __builtin_amdgcn_readlane(nrow, 16)),
-                    max(__builtin_amdgcn_readlane(nrow, 32), __builtin_amdgcn_readlane(nrow, 48)));
-    if (niter <= 0) return;
+    const int lane16 = threadIdx.x & 15;
+    const int xo = g.xo, yo0 = g.yo0, nrow = g.nrow, niter = g.niter;
     const int W = J.W;
     const int ymax = J.H - 1;
     const int yin0 = yo0 + OFF - 2;                  // input row of window slot 0
+    const int tlast = niter + 3;                     // last input row slot needed
 
-    // fast path: load columns and halo columns (fixed for the whole tile)
-    const int ldx = xo < W ? xo : ((W - 1) & ~(PPL - 1));
+    // load columns: the lane's aligned block and the group's outer halo dwords
+    const unsigned ldx = xo < W ? xo : ((W - 1) & ~(PPL - 1));
     const int hxr = xo + PPL;
-    const int hx = lane16 == 0 ? (xo >= 4 ? xo - 4 : 0)
-                 : (lane16 == 15 ? (hxr < W ? hxr : ((W - 1) & ~3)) : ldx);
-    const bool fix_right = (tx + 1) * TW + 4 > W;    // wave-uniform
-    const bool fix_left = tx == 0;
+    const unsigned hx = lane16 == 0 ? (xo >= 4 ? xo - 4 : 0)
+                      : (lane16 == 15 ? (hxr < W ? hxr : ((W - 1) & ~3)) : ldx);
+    const bool fix_right = FAST ? false : g.fix_right;
+    const bool fix_left = FAST ? false : g.fix_left;
 
     const uint8_t *src = J.src;
     const int64_t pitch = J.src_pitch;
     auto rowp = [&](int t) { return src + (int64_t)clampi(yin0 + t, 0, ymax) * pitch; };
 
-    // Rings indexed by input row mod 5.  Live ranges are short: an unpacked
-    // row lives 3 steps, v_s (A2, indexed by its centre row) 3 steps, the row
-    // filters 5 steps.
+    // Rings indexed by input row mod 5 (A2 and B by the row they are centred
+    // on).  Live ranges are short: an unpacked row lives 3 steps, v_s (A2) and
+    // the pair sums B 2-3 steps, the row filters 5 steps.
     v2s Rr[5][NP + 4];
-    v2s A2r[5][NP + 4];
+    v2s A2r[5][NP + 4], Br[5][NP + 4];
     v2s HR[5][NP], HS[5][NP];
     RawRow<PPL> raw[5];
 
+    // FAST waves load a row past the end as a repeat of the last needed row
+    // (a cache hit) instead of branching around the load.
     auto fetch = [&](int t, RawRow<PPL> &r) {
-        if constexpr (ALIGNED) load_row<PPL>(r, rowp(t), ldx, hx);
+        if constexpr (ALIGNED) load_row<PPL>(r, rowp(FAST ? min(t, tlast) : t), ldx, hx);
+    };
+    auto fetch_if = [&](int t, RawRow<PPL> &r) {
+        if (FAST || t <= tlast) fetch(t, r);
     };
     auto process = [&](int t, RawRow<PPL> &r, v2s (&R)[NP + 4], v2s (&hr)[NP], v2s (&hs)[NP]) {
         Win<PPL> w;
@@ -412,59 +448,124 @@ __device__ void wave_tile(const U8Job &J, int wt, int TH)
     // their slots), then rows 5 .. 3 + kPD.  Row t always lives in raw[t % 5].
     static_assert(kPD >= 1 && kPD <= 4, "prefetch distance must fit the 5-slot ring");
 #pragma unroll
-    for (int t = 0; t < 5; ++t)
-        if (t <= niter + 3) fetch(t, raw[t]);
+    for (int t = 0; t < 5; ++t) fetch_if(t, raw[t]);
 #pragma unroll
     for (int t = 0; t < 4; ++t) process(t, raw[t], Rr[t], HR[t], HS[t]);
 #pragma unroll
-    for (int t = 5; t < 4 + kPD; ++t)
-        if (t <= niter + 3) fetch(t, raw[t % 5]);
+    for (int t = 5; t < 4 + kPD; ++t) fetch_if(t, raw[t % 5]);
 #pragma unroll
     for (int c = 0; c < NP + 4; ++c) {
-        A2r[1][c] = Rr[2][c] - Rr[0][c];
-        A2r[2][c] = Rr[3][c] - Rr[1][c];
+        A2r[1][c] = Rr[2][c] - Rr[0][c];        // v_s centred on row 1
+        A2r[2][c] = Rr[3][c] - Rr[1][c];        // v_s centred on row 2
+        Br[2][c] = A2r[1][c] + A2r[2][c];       // B(2) = v_s(1) + v_s(2)
     }
 
-    // step i: input row t = i + 4 enters; output row i has its centre at t - 2
+    // step i: input row t = i + 4 enters; output row i has its centre at t - 2.
+    // v_r(y) = v_s(y-1) + 2 v_s(y) + v_s(y+1) = B(y) + B(y+1).
     auto step = [&](int i, auto phase) {
         constexpr int p = decltype(phase)::value;
         constexpr int s0 = p, s1 = (p + 1) % 5, s2 = (p + 2) % 5, s3 = (p + 3) % 5, s4 = (p + 4) % 5;
         constexpr int sp = (p + 4 + kPD) % 5;
-        if (i + 4 + kPD <= niter + 3) fetch(i + 4 + kPD, raw[sp]);
+        fetch_if(i + 4 + kPD, raw[sp]);
         process(i + 4, raw[s4], Rr[s4], HR[s4], HS[s4]);
         v2s vr[NP + 4];
 #pragma unroll
         for (int c = 0; c < NP + 4; ++c) {
-            A2r[s3][c] = Rr[s4][c] - Rr[s2][c];                          // v_s at t - 1
-            vr[c] = A2r[s1][c] + A2r[s2][c] + A2r[s2][c] + A2r[s3][c];   // v_r at t - 2
+            A2r[s3][c] = Rr[s4][c] - Rr[s2][c];     // v_s(t-1)
+            Br[s3][c] = A2r[s2][c] + A2r[s3][c];    // B(t-1)
+            vr[c] = Br[s2][c] + Br[s3][c];          // v_r(t-2)
         }
-        v2s Gx[NP], Gp[NP], Gy[NP], Gm[NP];
-        responses_y<NP>(vr, A2r[s2], Gy, Gp);
-        responses_x<NP>(HR[s0], HR[s1], HR[s2], HR[s3], HR[s4], HS[s0], HS[s2], HS[s4], Gx, Gm);
-        store_row<NP, DIR>(J, yo0 + i, xo, i < nrow, Gx, Gp, Gy, Gm);
+        v2s Gx[NP], Hp[NP], Gy[NP], Hm[NP];
+        responses_y<NP>(vr, A2r[s2], Gy, Hp);
+        responses_x<NP>(HR[s0], HR[s1], HR[s2], HR[s3], HR[s4], HS[s0], HS[s2], HS[s4], Gx, Hm);
+        store_row<NP, DIR, FAST>(J, yo0 + i, xo, FAST || i < nrow, Gx, Hp, Gy, Hm);
+        // keep each row's work in its own scheduling region: interleaving
+        // rows buys little ILP and costs the registers of a second row
+        __builtin_amdgcn_sched_barrier(0);
     };
 
+    using P0 = std::integral_constant<int, 0>;
+    using P1 = std::integral_constant<int, 1>;
+    using P2 = std::integral_constant<int, 2>;
+    using P3 = std::integral_constant<int, 3>;
+    using P4 = std::integral_constant<int, 4>;
+    // (a main loop of whole 5-step blocks plus a remainder keeps ~80 more
+    // values live across the loop exit; the uniform breaks cost two SALU ops)
     for (int i = 0; i < niter; i += 5) {
-        step(i, std::integral_constant<int, 0>{});
+        step(i, P0{});
         if (i + 1 >= niter) break;
-        step(i + 1, std::integral_constant<int, 1>{});
+        step(i + 1, P1{});
         if (i + 2 >= niter) break;
-        step(i + 2, std::integral_constant<int, 2>{});
+        step(i + 2, P2{});
         if (i + 3 >= niter) break;
-        step(i + 3, std::integral_constant<int, 3>{});
+        step(i + 3, P3{});
         if (i + 4 >= niter) break;
-        step(i + 4, std::integral_constant<int, 4>{});
+        step(i + 4, P4{});
     }
 }
 
 constexpr int kWaves = 4;   // waves per workgroup
 
+// Waves per SIMD the single-image kernel is compiled for (register budget
+// 512 / waves): 16 pixels per lane needs ~220 VGPRs (2 waves), 8 pixels per
+// lane ~134 (3 waves), or 128 with a few spilled values (4 waves).
+#ifndef SOBEL4X5_WAVES_PPL16
+#define SOBEL4X5_WAVES_PPL16 2
+#endif
+#ifndef SOBEL4X5_WAVES_PPL8
+#define SOBEL4X5_WAVES_PPL8 3
+#endif
+
+// Single image.  Wave w takes tile strip w / nchunk (four tiles side by
+// side, so all groups walk the same rows and row addresses stay scalar) and
+// the (w % nchunk)-th of nchunk equal row ranges of it: every resident wave
+// gets the same amount of work and there is no tail of a second round.
 template <int PPL, int OFF, bool ALIGNED, bool DIR>
-__global__ __launch_bounds__(64 * kWaves) void k_u8_single(U8Job J, int TH)
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
+    PPL == 8 ? SOBEL4X5_WAVES_PPL8 : SOBEL4X5_WAVES_PPL16,
+    PPL == 8 ? SOBEL4X5_WAVES_PPL8 : SOBEL4X5_WAVES_PPL16))) void k_u8_single(U8Job J, int nchunk)
 {
-    const int w = blockIdx.x * kWaves + (threadIdx.x >> 6);
-    if (w >= J.nwt) return;
-    wave_tile<PPL, OFF, ALIGNED, DIR>(J, w, TH);
+    constexpr int TW = 16 * PPL;
+    const int w = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ntxw = (J.ntx + 3) >> 2;
+    if (w >= ntxw * nchunk) return;
+    const int strip = w / nchunk, k = w % nchunk;
+    const int y0 = (int)(((int64_t)k * J.Ho) / nchunk);
+    const int y1 = (int)(((int64_t)(k + 1) * J.Ho) / nchunk);
+    if (y1 <= y0) return;
+    const int grp = (threadIdx.x >> 4) & 3;
+    const int tx = strip * 4 + grp;
+    Sweep g;
+    g.xo = tx * TW + (threadIdx.x & 15) * PPL;
+    g.yo0 = y0;
+    g.niter = y1 - y0;
+    g.nrow = tx < J.ntx ? g.niter : 0;
+    g.fix_right = (strip * 4 + 4) * TW + 4 > J.W;
+    g.fix_left = OFF == 0 && strip == 0;
+    const bool fast = ALIGNED && !g.fix_right && !g.fix_left && strip * 4 + 3 < J.ntx &&
+                      (J.mag == nullptr || J.mag_vec) && (!DIR || J.dir_vec);
+    if (fast)
+        sweep<PPL, OFF, ALIGNED, DIR, true>(J, g);
+    else
+        sweep<PPL, OFF, ALIGNED, DIR, false>(J, g);
+}
+
+// Geometry of wave-tile wt of image J in the batched kernel: four tiles of
+// th rows stacked in one tile column (narrow images then idle few lanes).
+__device__ __forceinline__ Sweep batch_geometry(const U8Job &J, int wt, int ppl, int th)
+{
+    const int tw = 16 * ppl;
+    const int tx = wt % J.ntx;
+    const int ty = (wt / J.ntx) * 4 + ((threadIdx.x >> 4) & 3);
+    Sweep g;
+    g.xo = tx * tw + (threadIdx.x & 15) * ppl;
+    g.yo0 = ty * th;
+    g.nrow = ty < J.nty ? min(th, J.Ho - g.yo0) : 0;
+    g.niter = max(max(__builtin_amdgcn_readlane(g.nrow, 0), __builtin_amdgcn_readlane(g.nrow, 16)),
+                  max(__builtin_amdgcn_readlane(g.nrow, 32), __builtin_amdgcn_readlane(g.nrow, 48)));
+    g.fix_right = (tx + 1) * tw + 4 > J.W;
+    g.fix_left = tx == 0;
+    return g;
 }
 
 // Persistent work-queue kernel: every wave takes the next wave-tile of the
@@ -489,7 +590,15 @@ __global__ __launch_bounds__(64 * kWaves) void k_u8_batched(const U8Job *__restr
             if (prefix[mid] <= (int)t) lo = mid; else hi = mid;
         }
         const U8Job J = jobs[lo];
-        wave_tile<PPL, OFF, ALIGNED, false>(J, (int)t - prefix[lo], TH);
+        Sweep g = batch_geometry(J, (int)t - prefix[lo], PPL, TH);
+        g.fix_left = g.fix_left && OFF == 0;
+        if (g.niter <= 0) continue;
+        const int full = __builtin_amdgcn_readlane(g.nrow, 0) == TH && __builtin_amdgcn_readlane(g.nrow, 16) == TH &&
+                         __builtin_amdgcn_readlane(g.nrow, 32) == TH && __builtin_amdgcn_readlane(g.nrow, 48) == TH;
+        if (ALIGNED && full && !g.fix_right && !g.fix_left && J.mag_vec)
+            sweep<PPL, OFF, ALIGNED, false, true>(J, g);
+        else
+            sweep<PPL, OFF, ALIGNED, false, false>(J, g);
     }
     if (lane == 0) {
         __threadfence();
@@ -502,21 +611,61 @@ __global__ __launch_bounds__(64 * kWaves) void k_u8_batched(const U8Job *__restr
     }
 }
 
-__global__ void k_round_mag(const int32_t *s2, uint8_t *out, int64_t n)
+// Plain streaming copy (16 bytes per lane per iteration, grid-stride): the
+// reference point for the achievable HBM bandwidth and for calibrating the
+// memory-traffic counters.
+__global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int64_t n16)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+}
+
+__global__ void k_round_mag(const int32_t *S, uint8_t *out, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = (uint8_t)round_mag(s2[i]);
+    if (i < n) out[i] = (uint8_t)round_mag(S[i]);
+}
+
+template <int PPL, int OFF, bool ALIGNED, bool DIR>
+const void *single_fn()
+{
+    return reinterpret_cast<const void *>(&k_u8_single<PPL, OFF, ALIGNED, DIR>);
+}
+
+// Resident waves of a kernel on this device (cached per kernel).
+int resident_waves(const void *fn)
+{
+    static std::mutex mu;
+    static std::vector<std::pair<const void *, int>> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto &e : cache)
+        if (e.first == fn) return e.second;
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * kWaves, 0) != hipSuccess)
+        return 0;
+    const int w = std::max(1, per_cu) * ncu * kWaves;
+    cache.emplace_back(fn, w);
+    return w;
 }
 
 template <int PPL, int OFF, bool DIR>
 hipError_t launch_single_t(const U8Job &j, const U8Shape &s, hipStream_t st)
 {
-    const int grid = (j.nwt + kWaves - 1) / kWaves;
-    if (u8_rows_aligned(j))
-        hipLaunchKernelGGL((k_u8_single<PPL, OFF, true, DIR>), dim3(grid), dim3(64 * kWaves), 0, st, j, s.th);
-    else
-        hipLaunchKernelGGL((k_u8_single<PPL, OFF, false, DIR>), dim3(grid), dim3(64 * kWaves), 0, st, j, s.th);
-    return hipGetLastError();
+    const bool aligned = u8_rows_aligned(j);
+    const void *fn = aligned ? single_fn<PPL, OFF, true, DIR>() : single_fn<PPL, OFF, false, DIR>();
+    const int ntxw = (j.ntx + 3) / 4;
+    int slots = s.waves > 0 ? s.waves : resident_waves(fn);
+    if (slots <= 0) slots = 2048;
+    // equal row ranges per strip, at least 8 rows each
+    int nchunk = std::max(1, slots / std::max(1, ntxw));
+    nchunk = std::min(nchunk, std::max(1, j.Ho / 8));
+    const int64_t waves = (int64_t)ntxw * nchunk;
+    const int grid = (int)((waves + kWaves - 1) / kWaves);
+    U8Job jj = j;
+    void *args[] = {(void *)&jj, (void *)&nchunk};
+    return hipLaunchKernel(fn, dim3(grid), dim3(64 * kWaves), args, 0, st);
 }
 
 template <int PPL, int OFF>
@@ -552,6 +701,7 @@ void u8_tile(U8Job &j, const U8Shape &s)
     j.nty = (j.Ho + s.th - 1) / s.th;
     j.nty4 = (j.nty + 3) / 4;
     j.nwt = j.ntx * j.nty4;
+    j.nwt_h = ((j.ntx + 3) / 4) * j.nty;
     j.mag_vec = ((reinterpret_cast<uintptr_t>(j.mag) | (uintptr_t)j.mag_pitch) & 15u) == 0;
     uintptr_t da = (uintptr_t)j.dir_pitch;
     for (int k = 0; k < 4; ++k) da |= reinterpret_cast<uintptr_t>(j.dir[k]);
@@ -560,7 +710,7 @@ void u8_tile(U8Job &j, const U8Shape &s)
 
 hipError_t launch_u8_single(const U8Job &j, int border_valid, const U8Shape &s, hipStream_t st)
 {
-    if (j.nwt <= 0) return hipSuccess;
+    if (j.ntx <= 0 || j.Ho <= 0) return hipSuccess;
     if (s.ppl == 16)
         return border_valid ? launch_single_d<16, 2>(j, s, st) : launch_single_d<16, 0>(j, s, st);
     return border_valid ? launch_single_d<8, 2>(j, s, st) : launch_single_d<8, 0>(j, s, st);
@@ -587,11 +737,23 @@ int u8_persistent_grid(const U8Shape &s, int border_valid, bool aligned)
     return ncu * per_cu;
 }
 
-hipError_t launch_round_mag(const int32_t *s2, uint8_t *out, int64_t n, hipStream_t st)
+hipError_t launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t st)
+{
+    if (n16 <= 0) return hipSuccess;
+    int dev = 0, ncu = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    int64_t blocks = std::min<int64_t>((n16 + 255) / 256, (int64_t)ncu * 16);
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<const uint4 *>(src),
+                       static_cast<uint4 *>(dst), n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_round_mag(const int32_t *S, uint8_t *out, int64_t n, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(k_round_mag, dim3((unsigned)blocks), dim3(256), 0, st, s2, out, n);
+    hipLaunchKernelGGL(k_round_mag, dim3((unsigned)blocks), dim3(256), 0, st, S, out, n);
     return hipGetLastError();
 }
 
