@@ -22,6 +22,14 @@ import numpy as np
 
 METRIC = "Gpixel/s + % of HBM peak, 4-dir 5x5 Sobel, uint8 8192² and mixed-size batch"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+# Vector ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12 32-bit
+# lane operations per second (one VALU instruction of a wave64 occupies a SIMD
+# for 4 cycles).  Packed int16 instructions count once: they are one issue.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU instructions per output pixel of the magnitude-only interior path:
+# 1764 in the 5-row unrolled loop body of k_u8_single<16, replicate, aligned,
+# mag-only>, which makes 5 rows x 16 pixels per lane (counted in its ISA).
+U8_VALU_OPS_PER_PX = 1764 / 80.0
 N = 8192
 ROTATE_BYTES = 2 << 30         # >= 1 GiB of distinct buffers (Infinity Cache is 256 MB)
 
@@ -35,9 +43,16 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
-    p.add_argument("--only", choices=["u8", "batched", "f32", "sweep", "copy"], default=None)
+    p.add_argument("--only", default=None,
+                   help="comma-separated subset of: u8, copy, sweep, batched, f32")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    return p.parse_args()
+    a = p.parse_args()
+    if a.only is not None:
+        a.only = set(x.strip() for x in a.only.split(",") if x.strip())
+        bad = a.only - {"u8", "copy", "sweep", "batched", "f32"}
+        if bad:
+            p.error("unknown --only part(s): %s" % ", ".join(sorted(bad)))
+    return a
 
 
 def time_launches(torch, fn, steps, warmup):
@@ -191,6 +206,23 @@ def bench_copy(torch, api, dev, steps):
     return {"bytes_moved": 2 * n, "ms": round(ms, 4), "GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+# HBM bytes per launch of the headline kernel from rocprofv3 --pmc FETCH_SIZE
+# and WRITE_SIZE (KiB per dispatch), scaled by what the same counters read for
+# the plain copy kernel (sobel4x5_debug_copy) of known size.  Valid only for
+# the kernel source they were taken on (its SHA-256 prefix); None otherwise.
+U8_TRAFFIC = {"src_sha256": None, "bytes": None}
+
+
+def u8_traffic():
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2305_00515_amd", "csrc", "sobel4x5_u8.hip")
+    try:
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    return U8_TRAFFIC["bytes"] if h == U8_TRAFFIC["src_sha256"] else None
+
+
 def cpu_baseline(img):
     """The CPU oracle (as it stands) on the same 8192x8192 image, all cores."""
     import oracle
@@ -198,7 +230,7 @@ def cpu_baseline(img):
     cores = len(os.sched_getaffinity(0))
     runs = []
     t_total = 0.0
-    while len(runs) < 3 and (t_total < 10.0 or not runs):
+    while t_total < 10.0 and len(runs) < 200:
         t0 = time.perf_counter()
         oracle.sobel_u8(img, want_dir=False, nthreads=cores)
         dt = time.perf_counter() - t0
@@ -213,9 +245,10 @@ def cpu_baseline(img):
                 break
     except OSError:
         pass
-    return {"value": round(img.size / best / 1e9, 4), "unit": "Gpixel/s", "cores": cores, "kind": "oracle",
-            "sample": "the full 8192x8192 uint8 image, magnitude only, %d run(s), best %.2f s; CPU %s"
-                      % (len(runs), best, model)}
+    return {"value": round(len(runs) * img.size / t_total / 1e9, 4), "unit": "Gpixel/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "the full 8192x8192 uint8 image (magnitude only) repeated for >= 10 s: %d run(s), "
+                      "best %.3f s; CPU %s" % (len(runs), best, model)}
 
 
 def main():
@@ -236,12 +269,13 @@ def main():
     line = {"metric": METRIC, "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
             "data": "synthetic"}
-    only = args.only
+    want = (lambda part: args.only is None or part in args.only)
     img = None
-    if only in (None, "u8"):
+    if want("u8"):
         log("u8 8192x8192 magnitude: %d steps" % args.steps)
         r, img = bench_u8(torch, api, synth, dev, args.steps, args.warmup)
-        achieved = r["alg_bytes"] / (r["ms"] * 1e-3) / 1e9
+        gbs = r["alg_bytes"] / (r["ms"] * 1e-3) / 1e9
+        tops = U8_VALU_OPS_PER_PX * N * N / (r["ms"] * 1e-3) / 1e12
         line.update({
             "value": round(r["gpx"], 2), "ms_per_step": round(r["ms"], 5),
             "config": {"workload": "uint8 8192x8192 four-directional 5x5 Sobel, uint8 magnitude only, "
@@ -249,21 +283,24 @@ def main():
                        "image": "rect_image(8192, 8192, seed=3): uniform noise + 20 filled rectangles",
                        "bytes_per_px": 2, "rotating_buffers_gib": round(r["rotating_gib"], 2),
                        "hot_same_buffer_ms": round(r["hot_ms"], 5)},
-            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                         "kernel": "k_u8_single<16,0,aligned,mag-only>",
-                         "alg_bytes_per_launch": r["alg_bytes"]},
+            "roofline": {"bound": "alu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                         "unit": "TOP/s", "frac": round(tops / VALU_PEAK_TOPS, 4),
+                         "traffic": u8_traffic(),
+                         "kernel": "k_u8_single<16,replicate,aligned,mag-only>",
+                         "valu_ops_per_px": round(U8_VALU_OPS_PER_PX, 3),
+                         "alg_bytes_per_launch": r["alg_bytes"], "hbm_GBps": round(gbs, 1),
+                         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)},
         })
-    if only in (None, "copy"):
+    if want("copy"):
         log("copy ceiling")
         line["copy_ceiling"] = bench_copy(torch, api, dev, args.steps)
-    if only in (None, "sweep"):
+    if want("sweep"):
         log("sweep")
         line["sweep"] = bench_sweep(torch, api, synth, dev, args.steps, args.warmup)
-    if only in (None, "batched"):
+    if want("batched"):
         log("batched 256 images")
         line["batched"] = bench_batched(torch, api, synth, dev, args.steps, args.warmup)
-    if only in (None, "f32"):
+    if want("f32"):
         log("fp32 32x1024^2 fwd+bwd")
         line["f32"] = bench_f32(torch, api, synth, dev, args.steps, args.warmup)
     if img is not None and not args.no_cpu_baseline:

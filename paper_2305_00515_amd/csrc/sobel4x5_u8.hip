@@ -37,6 +37,7 @@
 //     are replaced by the last valid pixel (replicate).
 
 #include "internal.hpp"
+#include "load_columns.hpp"
 
 #include <algorithm>
 #include <mutex>
@@ -407,10 +408,8 @@ __device__ void sweep(const U8Job &J, const Sweep &g)
     const int tlast = niter + 3;                     // last input row slot needed
 
     // load columns: the lane's aligned block and the group's outer halo dwords
-    const unsigned ldx = xo < W ? xo : ((W - 1) & ~(PPL - 1));
-    const int hxr = xo + PPL;
-    const unsigned hx = lane16 == 0 ? (xo >= 4 ? xo - 4 : 0)
-                      : (lane16 == 15 ? (hxr < W ? hxr : ((W - 1) & ~3)) : ldx);
+    const LoadCols lc = load_columns(xo, lane16, W, PPL);
+    const unsigned ldx = lc.ldx, hx = lc.hx;
     const bool fix_right = FAST ? false : g.fix_right;
     const bool fix_left = FAST ? false : g.fix_left;
 
