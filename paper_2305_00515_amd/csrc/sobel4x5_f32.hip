@@ -41,15 +41,16 @@ constexpr int kHaloB = 6, kOwnB = 64 - 2 * kHaloB;   // adjoint: 52 columns per 
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// value held by lane + 1 / lane - 1 (wave-wide DPP shift; the last / first
-// lane gets 0, which no kept column uses)
+// value held by lane + 1 / lane - 1 (wave-wide DPP shift; bound_ctrl gives
+// the last / first lane 0, which no kept column uses, and lets the move
+// write its destination without first clearing it)
 __device__ __forceinline__ float from_right(float v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float from_left(float v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
 }
 
 // Row filters of one row across the lanes (Eq. (Fx) and the D term of
@@ -87,9 +88,23 @@ __device__ __forceinline__ void hcombine(float vr, float vs, float &C, float &Cd
     Cd = comb_cd(l2, l1, vr, r1, r2, t2, vs, s2);
 }
 
+__device__ __forceinline__ float sum_sq(float Gx, float Gy, float Gp, float Gm)
+{
+    return Gx * Gx + Gy * Gy + 0.5f * (Gp * Gp + Gm * Gm);
+}
+
+// M = sqrt(S) by the hardware square root (within 1 ulp; below S = 2^-100,
+// i.e. M < 1e-15, its error is an absolute one far under the tolerance).
 __device__ __forceinline__ float mag_of(float Gx, float Gy, float Gp, float Gm)
 {
-    return sqrtf(Gx * Gx + Gy * Gy + 0.5f * (Gp * Gp + Gm * Gm));
+    return __builtin_amdgcn_sqrtf(sum_sq(Gx, Gy, Gp, Gm));
+}
+
+// g / M = g / sqrt(S) for S > 0, 0 for S = 0: the hardware reciprocal square
+// root (within 1 ulp) for normal S, the exact library route below 2^-100.
+__device__ __forceinline__ float scale_of(float g, float S)
+{
+    return S >= 0x1p-100f ? g * __builtin_amdgcn_rsqf(S) : (S > 0.f ? g / sqrtf(S) : 0.f);
 }
 
 template <int P>
@@ -244,9 +259,8 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
         const float vr = (X[s4] - X[s0]) + 2.0f * vs;
         float Gy, Gp;
         hcombine(vr, vs, Gy, Gp);
-        const float M = mag_of(Gx, Gy, Gp, Gm);
         const float gq = pfg[p];                 // grad of the output row centred on q
-        const float sc = M > 0.f ? gq / M : 0.f;
+        const float sc = scale_of(gq, sum_sq(Gx, Gy, Gp, Gm));
         const float wx = sc * Gx, wy = sc * Gy, wp = 0.5f * sc * Gp, wm = 0.5f * sc * Gm;
         // w rings hold centre rows q-4 .. q in slots (p+1)%5 .. p as well
         WY[s4] = wy;
