@@ -267,6 +267,38 @@ __device__ __forceinline__ Win<PPL> finish_row(RawRow<PPL> &r, int lane16, int x
     return w;
 }
 
+// Replicate fix-ups of the group halo dwords for a fast wave at the image's
+// left / right edge (its lanes' own blocks all lie inside the row): loop-
+// invariant per-lane masks, so the fix-up is two v_perm + two v_bfi per row
+// and no branch.  mask bits set = keep the loaded byte.
+struct EdgeFix {
+    u32 keep_l;   // lane 0 at column 0 (replicate border): 0, else all ones
+    u32 keep_r;   // lane 15 whose halo reaches column W: bytes < W - (xo + ppl), else all ones
+    u32 sel_r;    // v_perm selector replicating the byte of column W-1 from (hw, last own dword)
+};
+
+template <int PPL, int OFF>
+__device__ __forceinline__ EdgeFix edge_fix(int lane16, int xo, int W, bool at_left, bool at_right)
+{
+    EdgeFix e;
+    e.keep_l = (OFF == 0 && at_left && lane16 == 0 && xo == 0) ? 0u : ~0u;
+    const int nh = W - (xo + PPL);   // valid bytes of the right halo dword (>= 0 here)
+    const bool r = at_right && lane16 == 15 && nh < 4;
+    e.keep_r = r ? ((1u << (8 * nh)) - 1u) : ~0u;
+    e.sel_r = (nh >= 1 ? (u32)(4 + nh - 1) : 3u) * 0x01010101u;
+    return e;
+}
+
+template <int PPL>
+__device__ __forceinline__ void apply_edge(RawRow<PPL> &r, const EdgeFix &e)
+{
+    constexpr int ND = PPL / 4;
+    const u32 fr = perm(r.hw, r.d[ND - 1], e.sel_r);   // column W-1, four times
+    const u32 fl = perm(r.d[0], r.d[0], 0u);            // column 0, four times
+    r.hw = (r.hw & e.keep_r) | (fr & ~e.keep_r);
+    r.hw = (r.hw & e.keep_l) | (fl & ~e.keep_l);
+}
+
 // Slow path for rows that are not 16-byte aligned: every window byte is read
 // on its own at its clamped column.
 template <int PPL>
@@ -396,9 +428,10 @@ struct Sweep {
 // Sweep the wave's tiles top to bottom.  FAST: an interior wave (no border
 // fix-ups, every group active for all niter rows, aligned rows and outputs):
 // the loop body has no branches, so the compiler can schedule across steps.
-template <int PPL, int OFF, bool ALIGNED, bool DIR, bool FAST>
+template <int PPL, int OFF, bool ALIGNED, bool DIR, bool FAST, bool EDGE>
 __device__ void sweep(const U8Job &J, const Sweep &g)
 {
+    static_assert(!EDGE || FAST, "edge fix-ups by mask exist for fast waves only");
     constexpr int NP = PPL / 2;
     const int lane16 = threadIdx.x & 15;
     const int xo = g.xo, yo0 = g.yo0, nrow = g.nrow, niter = g.niter;
@@ -412,6 +445,7 @@ __device__ void sweep(const U8Job &J, const Sweep &g)
     const unsigned ldx = lc.ldx, hx = lc.hx;
     const bool fix_right = FAST ? false : g.fix_right;
     const bool fix_left = FAST ? false : g.fix_left;
+    const EdgeFix efix = edge_fix<PPL, OFF>(lane16, xo, W, EDGE && g.fix_left, EDGE && g.fix_right);
 
     const uint8_t *src = J.src;
     const int64_t pitch = J.src_pitch;
@@ -435,6 +469,7 @@ __device__ void sweep(const U8Job &J, const Sweep &g)
     };
     auto process = [&](int t, RawRow<PPL> &r, v2s (&R)[NP + 4], v2s (&hr)[NP], v2s (&hs)[NP]) {
         Win<PPL> w;
+        if constexpr (EDGE) apply_edge<PPL>(r, efix);
         if constexpr (ALIGNED)
             w = finish_row<PPL, OFF>(r, lane16, xo, W, fix_right, fix_left);
         else
@@ -541,12 +576,17 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
     g.nrow = tx < J.ntx ? g.niter : 0;
     g.fix_right = (strip * 4 + 4) * TW + 4 > J.W;
     g.fix_left = OFF == 0 && strip == 0;
-    const bool fast = ALIGNED && !g.fix_right && !g.fix_left && strip * 4 + 3 < J.ntx &&
+    // fast: all four tiles complete (every lane's block and output inside
+    // the image) and vector-aligned outputs; the strips at the image edges
+    // take the fast path with mask fix-ups of their group halos
+    const bool fast = ALIGNED && (strip * 4 + 4) * TW <= J.Wo &&
                       (J.mag == nullptr || J.mag_vec) && (!DIR || J.dir_vec);
-    if (fast)
-        sweep<PPL, OFF, ALIGNED, DIR, true>(J, g);
+    if (fast && !g.fix_right && !g.fix_left)
+        sweep<PPL, OFF, ALIGNED, DIR, true, false>(J, g);
+    else if (fast)
+        sweep<PPL, OFF, ALIGNED, DIR, true, true>(J, g);
     else
-        sweep<PPL, OFF, ALIGNED, DIR, false>(J, g);
+        sweep<PPL, OFF, ALIGNED, DIR, false, false>(J, g);
 }
 
 // Geometry of wave-tile wt of image J in the batched kernel: four tiles of
@@ -594,10 +634,14 @@ __global__ __launch_bounds__(64 * kWaves) void k_u8_batched(const U8Job *__restr
         if (g.niter <= 0) continue;
         const int full = __builtin_amdgcn_readlane(g.nrow, 0) == TH && __builtin_amdgcn_readlane(g.nrow, 16) == TH &&
                          __builtin_amdgcn_readlane(g.nrow, 32) == TH && __builtin_amdgcn_readlane(g.nrow, 48) == TH;
-        if (ALIGNED && full && !g.fix_right && !g.fix_left && J.mag_vec)
-            sweep<PPL, OFF, ALIGNED, false, true>(J, g);
+        const int tx = (int)(t - prefix[lo]) % J.ntx;
+        const bool fast = ALIGNED && full && (tx + 1) * 16 * PPL <= J.Wo && J.mag_vec;
+        if (fast && !g.fix_right && !g.fix_left)
+            sweep<PPL, OFF, ALIGNED, false, true, false>(J, g);
+        else if (fast)
+            sweep<PPL, OFF, ALIGNED, false, true, true>(J, g);
         else
-            sweep<PPL, OFF, ALIGNED, false, false>(J, g);
+            sweep<PPL, OFF, ALIGNED, false, false, false>(J, g);
     }
     if (lane == 0) {
         __threadfence();

@@ -117,3 +117,12 @@ def test_config3_full_batch_vs_single_image_path(oracle_mod, sobel_lib, gpu):
         xs = np.concatenate([rng.integers(0, w, 300), [0, 0, w - 1, w - 1]])
         om, _ = oracle_mod.sobel_u8_points(img, ys, xs)
         assert np.array_equal(m.cpu().numpy()[ys, xs], om), "image %d" % i
+
+
+def test_edge_tiles_fast_path(oracle_mod, sobel_lib, gpu):
+    """Aligned images whose first and last tile columns are complete: the
+    edge tiles take the fast path with mask fix-ups of the group halo."""
+    sizes = [(130, 512), (97, 1024), (64, 1027), (200, 2048), (33, 515), (128, 4096)]
+    imgs, srcs, mags = make_batch(sizes, gpu)
+    sobel_lib.Plan(srcs, mags).launch()
+    check_all(oracle_mod, imgs, mags)

@@ -184,3 +184,19 @@ def test_errors_raise_and_enqueue_nothing(sobel_lib, gpu):
     assert e.value.code == sobel_lib.EINVAL
     with pytest.raises(sobel_lib.SobelError):
         sobel_lib.sobel4x5_u8(src, mag=src)            # output overlaps input
+
+
+@pytest.mark.parametrize("w", [512, 513, 514, 515, 1024, 1025, 1026, 1027, 2048, 2051])
+def test_edge_strip_widths(oracle_mod, sobel_lib, gpu, w):
+    """Widths at and just past a multiple of a wave's four tiles (8 or 16
+    pixels per lane), aligned rows: the strips at the left and right image
+    edge run the fast path with mask fix-ups of the group halo (0..3 valid
+    bytes of the right halo dword)."""
+    img = synth.rect_image(45, w, 31 * w)
+    p = synth.round_up(w, 16)
+    for border in (0, 1):
+        wo = w - 4 * border
+        check(oracle_mod, sobel_lib, img, gpu, border, 0, pitch=p, mag_pitch=synth.round_up(wo, 16))
+    # low amplitude: unsaturated magnitudes near the edges
+    low = (img % 3).astype(np.uint8)
+    check(oracle_mod, sobel_lib, low, gpu, 0, 0, pitch=p, mag_pitch=p)
