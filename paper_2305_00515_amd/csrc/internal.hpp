@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace s4x5 {
 
@@ -52,13 +53,20 @@ hipError_t launch_u8_single(const U8Job &j, int border_valid, const U8Shape &s,
                             hipStream_t stream);
 
 // Batched persistent launch (`aligned`: every image has 16-byte aligned src
-// rows).  `jobs` (device) holds `count` images whose
-// wave-tile counts have exclusive prefix sums `wt_prefix` (device, count+1
-// entries); `queue` (device, 2 words, zero before the first launch) is the
-// work counter and the exit counter, reset by the last wave to finish.
-hipError_t launch_u8_batched(const U8Job *jobs, const int32_t *wt_prefix, int32_t count,
-                             uint32_t *queue, int border_valid, bool aligned, const U8Shape &s,
-                             int grid, hipStream_t stream);
+// rows).  `jobs` (device) holds the images; `tiles` (device, `total`
+// entries) lists every wave-tile of the batch as {image, kind, tx, ty}
+// (batched_tiles); `queue` (device, 2 words, zero before the first launch)
+// is the work counter and the exit counter, reset by the last wave to
+// finish.
+hipError_t launch_u8_batched(const U8Job *jobs, const int4 *tiles, int32_t total, uint32_t *queue,
+                             int border_valid, bool aligned, const U8Shape &s, int grid,
+                             hipStream_t stream);
+
+// Wave-tiles of image `img` (tiled by u8_tile) appended to `out`: the
+// complete four-tile strips side by side (kind 0, one per strip and row
+// block), then the remaining tile columns with four row blocks stacked
+// (kind 1).
+void batched_tiles(const U8Job &j, int32_t img, std::vector<int4> &out);
 
 // Number of workgroups of the persistent kernel that fit on the device at
 // once for shape `s` (occupancy x CUs), or 0 on error.

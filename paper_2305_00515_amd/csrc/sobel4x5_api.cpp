@@ -242,7 +242,8 @@ struct sobel4x5_plan_s {
     bool aligned = true;
     std::vector<sobel4x5_image> imgs;
     U8Job *d_jobs = nullptr;
-    int32_t *d_prefix = nullptr;
+    int4 *d_tiles = nullptr;      // {image, kind, tx, ty} per queue ticket
+    int32_t total = 0;            // wave-tiles of the batch
     uint32_t *d_queue = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -255,12 +256,12 @@ void plan_free_device(sobel4x5_plan_s *p)
     if (p->exec) hipGraphExecDestroy(p->exec);
     if (p->graph) hipGraphDestroy(p->graph);
     if (p->d_jobs) hipFree(p->d_jobs);
-    if (p->d_prefix) hipFree(p->d_prefix);
+    if (p->d_tiles) hipFree(p->d_tiles);
     if (p->d_queue) hipFree(p->d_queue);
     p->exec = nullptr;
     p->graph = nullptr;
     p->d_jobs = nullptr;
-    p->d_prefix = nullptr;
+    p->d_tiles = nullptr;
     p->d_queue = nullptr;
 }
 
@@ -271,7 +272,6 @@ int plan_setup(sobel4x5_plan_s *p, const U8Shape &shape)
     p->shape = shape;
     const int valid = p->border == SOBEL4X5_BORDER_VALID;
     std::vector<U8Job> jobs(p->count);
-    std::vector<int32_t> prefix(p->count + 1, 0);
     bool aligned = true;
     for (int32_t i = 0; i < p->count; ++i) {
         const sobel4x5_image &m = p->imgs[i];
@@ -280,20 +280,23 @@ int plan_setup(sobel4x5_plan_s *p, const U8Shape &shape)
         jobs[i] = make_job(m.src, m.width, m.height, m.src_pitch, Wo, Ho, m.mag, m.mag_pitch, nullptr, 0, 0);
         u8_tile(jobs[i], shape);
         aligned = aligned && u8_rows_aligned(jobs[i]);
-        int64_t next = (int64_t)prefix[i] + jobs[i].nwt;
-        if (next > INT32_MAX) return fail(SOBEL4X5_EINVAL, "batch too large for one plan");
-        prefix[i + 1] = (int32_t)next;
     }
     p->aligned = aligned;
+    std::vector<int4> tiles;
+    for (int32_t i = 0; i < p->count; ++i) {
+        batched_tiles(jobs[i], i, tiles);
+        if (tiles.size() > (size_t)INT32_MAX) return fail(SOBEL4X5_EINVAL, "batch too large for one plan");
+    }
+    p->total = (int32_t)tiles.size();
     hipError_t e;
     if ((e = hipMalloc(&p->d_jobs, sizeof(U8Job) * p->count)) != hipSuccess ||
-        (e = hipMalloc(&p->d_prefix, sizeof(int32_t) * (p->count + 1))) != hipSuccess ||
+        (e = hipMalloc(&p->d_tiles, sizeof(int4) * std::max<size_t>(1, tiles.size()))) != hipSuccess ||
         (e = hipMalloc(&p->d_queue, 2 * sizeof(uint32_t))) != hipSuccess) {
         plan_free_device(p);
         return fail(SOBEL4X5_ENOMEM, "hipMalloc for plan tables: %s", hipGetErrorString(e));
     }
     if ((e = hipMemcpy(p->d_jobs, jobs.data(), sizeof(U8Job) * p->count, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(p->d_prefix, prefix.data(), sizeof(int32_t) * (p->count + 1), hipMemcpyHostToDevice)) !=
+        (e = hipMemcpy(p->d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice)) !=
             hipSuccess ||
         (e = hipMemset(p->d_queue, 0, 2 * sizeof(uint32_t))) != hipSuccess) {
         plan_free_device(p);
@@ -304,14 +307,14 @@ int plan_setup(sobel4x5_plan_s *p, const U8Shape &shape)
         plan_free_device(p);
         return fail(SOBEL4X5_EHIP, "could not query occupancy");
     }
-    const int need = (prefix[p->count] + 3) / 4;   // never more workgroups than work
+    const int need = (p->total + 3) / 4;   // never more workgroups than work
     p->grid = std::max(1, std::min(p->grid, need));
     return ok();
 }
 
 int plan_direct_launch(sobel4x5_plan_s *p, hipStream_t st)
 {
-    hipError_t e = launch_u8_batched(p->d_jobs, p->d_prefix, p->count, p->d_queue,
+    hipError_t e = launch_u8_batched(p->d_jobs, p->d_tiles, p->total, p->d_queue,
                                      p->border == SOBEL4X5_BORDER_VALID, p->aligned, p->shape, p->grid, st);
     return e == hipSuccess ? ok() : hip_fail(e, "batched launch");
 }
@@ -447,10 +450,18 @@ void tune_store(const std::string &key, const U8Shape &s)
     std::fclose(f);
 }
 
+// Shape of a batched plan without autotuning: 16 pixels per lane, 32-row
+// tiles; SOBEL4X5_BATCH_PPL (8 or 16) and SOBEL4X5_BATCH_TH (4..256)
+// override it.
 U8Shape batch_default_shape(const std::vector<sobel4x5_image> &imgs)
 {
     (void)imgs;
-    return U8Shape{16, 32, 4};
+    U8Shape s{16, 32, 4};
+    const int ppl = env_int("SOBEL4X5_BATCH_PPL", 0);
+    if (ppl == 8 || ppl == 16) s.ppl = ppl;
+    const int th = env_int("SOBEL4X5_BATCH_TH", 0);
+    if (th >= 4 && th <= 256) s.th = th;
+    return s;
 }
 
 int plan_autotune(sobel4x5_plan_s *p)

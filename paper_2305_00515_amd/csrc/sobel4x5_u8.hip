@@ -589,53 +589,72 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
         sweep<PPL, OFF, ALIGNED, DIR, false, false>(J, g);
 }
 
-// Geometry of wave-tile wt of image J in the batched kernel: four tiles of
-// th rows stacked in one tile column (narrow images then idle few lanes).
-__device__ __forceinline__ Sweep batch_geometry(const U8Job &J, int wt, int ppl, int th)
+// Geometry of one wave-tile of the batched kernel, ti = {image, kind, tx, ty}
+// (built on the host):
+//   kind 0: four tiles side by side, tile columns tx .. tx+3 (a complete
+//           strip), rows [ty*th, ty*th + th): every group walks the same rows
+//           and each load instruction covers one contiguous row segment;
+//   kind 1: four tiles of th rows stacked in tile column tx (row blocks
+//           ty .. ty+3), for the columns an image has beyond its last
+//           complete strip.
+__device__ __forceinline__ Sweep batch_geometry(const U8Job &J, const int4 &ti, int ppl, int th)
 {
     const int tw = 16 * ppl;
-    const int tx = wt % J.ntx;
-    const int ty = (wt / J.ntx) * 4 + ((threadIdx.x >> 4) & 3);
+    const int grp = (threadIdx.x >> 4) & 3;
+    const int lane16 = threadIdx.x & 15;
     Sweep g;
-    g.xo = tx * tw + (threadIdx.x & 15) * ppl;
-    g.yo0 = ty * th;
-    g.nrow = ty < J.nty ? min(th, J.Ho - g.yo0) : 0;
-    g.niter = max(max(__builtin_amdgcn_readlane(g.nrow, 0), __builtin_amdgcn_readlane(g.nrow, 16)),
-                  max(__builtin_amdgcn_readlane(g.nrow, 32), __builtin_amdgcn_readlane(g.nrow, 48)));
-    g.fix_right = (tx + 1) * tw + 4 > J.W;
-    g.fix_left = tx == 0;
+    if (ti.y == 0) {
+        const int tx = ti.z + grp;
+        g.xo = tx * tw + lane16 * ppl;
+        g.yo0 = ti.w * th;
+        g.nrow = min(th, J.Ho - g.yo0);
+        g.niter = g.nrow;
+        g.fix_right = (ti.z + 4) * tw + 4 > J.W;
+        g.fix_left = ti.z == 0;
+    } else {
+        const int ty = ti.w + grp;
+        g.xo = ti.z * tw + lane16 * ppl;
+        g.yo0 = ty * th;
+        g.nrow = ty < J.nty ? min(th, J.Ho - g.yo0) : 0;
+        g.niter = max(max(__builtin_amdgcn_readlane(g.nrow, 0), __builtin_amdgcn_readlane(g.nrow, 16)),
+                      max(__builtin_amdgcn_readlane(g.nrow, 32), __builtin_amdgcn_readlane(g.nrow, 48)));
+        g.fix_right = (ti.z + 1) * tw + 4 > J.W;
+        g.fix_left = ti.z == 0;
+    }
     return g;
 }
 
 // Persistent work-queue kernel: every wave takes the next wave-tile of the
 // whole batch from queue[0] until none are left, then counts itself out in
-// queue[1]; the last wave out resets both words for the next launch.
+// queue[1]; the last wave out resets both words for the next launch.  A
+// ticket indexes the host-built tile table, so finding a tile is one load.
 template <int PPL, int OFF, bool ALIGNED>
 __global__ __launch_bounds__(64 * kWaves) void k_u8_batched(const U8Job *__restrict__ jobs,
-                                                            const int32_t *__restrict__ prefix,
-                                                            int32_t count, uint32_t *queue, int TH)
+                                                            const int4 *__restrict__ tiles, int32_t total,
+                                                            uint32_t *queue, int TH)
 {
+    constexpr int TW = 16 * PPL;
     const int lane = threadIdx.x & 63;
-    const int total = prefix[count];
     for (;;) {
-        u32 t = 0;
-        if (lane == 0) t = atomicAdd(&queue[0], 1u);
-        t = (u32)__builtin_amdgcn_readfirstlane((int)t);
-        if ((int)t >= total) break;
-        // image i with prefix[i] <= t < prefix[i+1] (wave-uniform search)
-        int lo = 0, hi = count;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (prefix[mid] <= (int)t) lo = mid; else hi = mid;
-        }
-        const U8Job J = jobs[lo];
-        Sweep g = batch_geometry(J, (int)t - prefix[lo], PPL, TH);
+        u32 tv = 0;
+        if (lane == 0) tv = atomicAdd(&queue[0], 1u);
+        const int t = __builtin_amdgcn_readfirstlane((int)tv);
+        if (t >= total) break;
+        const int4 ti = tiles[t];
+        const U8Job J = jobs[ti.x];
+        Sweep g = batch_geometry(J, ti, PPL, TH);
         g.fix_left = g.fix_left && OFF == 0;
         if (g.niter <= 0) continue;
-        const int full = __builtin_amdgcn_readlane(g.nrow, 0) == TH && __builtin_amdgcn_readlane(g.nrow, 16) == TH &&
-                         __builtin_amdgcn_readlane(g.nrow, 32) == TH && __builtin_amdgcn_readlane(g.nrow, 48) == TH;
-        const int tx = (int)(t - prefix[lo]) % J.ntx;
-        const bool fast = ALIGNED && full && (tx + 1) * 16 * PPL <= J.Wo && J.mag_vec;
+        // fast: every group has its full rows, every lane's block and output
+        // inside the image, vector-aligned output rows
+        bool fast;
+        if (ti.y == 0) {
+            fast = ALIGNED && (ti.z + 4) * TW <= J.Wo && J.mag_vec;
+        } else {
+            const bool full = __builtin_amdgcn_readlane(g.nrow, 0) == TH && __builtin_amdgcn_readlane(g.nrow, 16) == TH &&
+                              __builtin_amdgcn_readlane(g.nrow, 32) == TH && __builtin_amdgcn_readlane(g.nrow, 48) == TH;
+            fast = ALIGNED && full && (ti.z + 1) * TW <= J.Wo && J.mag_vec;
+        }
         if (fast && !g.fix_right && !g.fix_left)
             sweep<PPL, OFF, ALIGNED, false, true, false>(J, g);
         else if (fast)
@@ -751,6 +770,15 @@ void u8_tile(U8Job &j, const U8Shape &s)
     j.dir_vec = (da & 15u) == 0;
 }
 
+void batched_tiles(const U8Job &j, int32_t img, std::vector<int4> &out)
+{
+    const int strips = j.ntx / 4;
+    for (int ty = 0; ty < j.nty; ++ty)
+        for (int s = 0; s < strips; ++s) out.push_back(make_int4(img, 0, 4 * s, ty));
+    for (int tx = 4 * strips; tx < j.ntx; ++tx)
+        for (int ty = 0; ty < j.nty; ty += 4) out.push_back(make_int4(img, 1, tx, ty));
+}
+
 hipError_t launch_u8_single(const U8Job &j, int border_valid, const U8Shape &s, hipStream_t st)
 {
     if (j.ntx <= 0 || j.Ho <= 0) return hipSuccess;
@@ -759,12 +787,12 @@ hipError_t launch_u8_single(const U8Job &j, int border_valid, const U8Shape &s, 
     return border_valid ? launch_single_d<8, 2>(j, s, st) : launch_single_d<8, 0>(j, s, st);
 }
 
-hipError_t launch_u8_batched(const U8Job *jobs, const int32_t *prefix, int32_t count, uint32_t *queue,
+hipError_t launch_u8_batched(const U8Job *jobs, const int4 *tiles, int32_t total, uint32_t *queue,
                              int border_valid, bool aligned, const U8Shape &s, int grid, hipStream_t st)
 {
     const void *fn = pick_batched(s.ppl, border_valid, aligned);
     int th = s.th;
-    void *args[] = {(void *)&jobs, (void *)&prefix, (void *)&count, (void *)&queue, (void *)&th};
+    void *args[] = {(void *)&jobs, (void *)&tiles, (void *)&total, (void *)&queue, (void *)&th};
     return hipLaunchKernel(fn, dim3(grid), dim3(64 * kWaves), args, 0, st);
 }
 
