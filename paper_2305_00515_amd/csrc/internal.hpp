@@ -54,7 +54,7 @@ hipError_t launch_u8_single(const U8Job &j, int border_valid, const U8Shape &s,
 
 // Batched persistent launch (`aligned`: every image has 16-byte aligned src
 // rows).  `jobs` (device) holds the images; `tiles` (device, `total`
-// entries) lists every wave-tile of the batch as {image, kind, tx, ty}
+// entries) lists every wave-tile of the batch as {image, kind | rows << 1, tx, y0}
 // (batched_tiles); `queue` (device, 2 words, zero before the first launch)
 // is the work counter and the exit counter, reset by the last wave to
 // finish.
@@ -62,11 +62,12 @@ hipError_t launch_u8_batched(const U8Job *jobs, const int4 *tiles, int32_t total
                              int border_valid, bool aligned, const U8Shape &s, int grid,
                              hipStream_t stream);
 
-// Wave-tiles of image `img` (tiled by u8_tile) appended to `out`: the
-// complete four-tile strips side by side (kind 0, one per strip and row
-// block), then the remaining tile columns with four row blocks stacked
-// (kind 1).
-void batched_tiles(const U8Job &j, int32_t img, std::vector<int4> &out);
+// Wave-tiles of image `img` (tiled by u8_tile with th rows per tile): the
+// complete four-tile strips side by side (kind 0) in tall row chunks
+// (appended to `first`) and short ones (appended to `last`, queued after
+// every tall chunk of the batch), then the remaining tile columns with four
+// row blocks stacked (kind 1, in `first`).
+void batched_tiles(const U8Job &j, int32_t img, int th, std::vector<int4> &first, std::vector<int4> &last);
 
 // Number of workgroups of the persistent kernel that fit on the device at
 // once for shape `s` (occupancy x CUs), or 0 on error.

@@ -242,7 +242,7 @@ struct sobel4x5_plan_s {
     bool aligned = true;
     std::vector<sobel4x5_image> imgs;
     U8Job *d_jobs = nullptr;
-    int4 *d_tiles = nullptr;      // {image, kind, tx, ty} per queue ticket
+    int4 *d_tiles = nullptr;      // {image, kind | rows << 1, tx, y0} per queue ticket
     int32_t total = 0;            // wave-tiles of the batch
     uint32_t *d_queue = nullptr;
     hipGraph_t graph = nullptr;
@@ -282,11 +282,12 @@ int plan_setup(sobel4x5_plan_s *p, const U8Shape &shape)
         aligned = aligned && u8_rows_aligned(jobs[i]);
     }
     p->aligned = aligned;
-    std::vector<int4> tiles;
+    std::vector<int4> tiles, tail;
     for (int32_t i = 0; i < p->count; ++i) {
-        batched_tiles(jobs[i], i, tiles);
-        if (tiles.size() > (size_t)INT32_MAX) return fail(SOBEL4X5_EINVAL, "batch too large for one plan");
+        batched_tiles(jobs[i], i, shape.th, tiles, tail);
+        if (tiles.size() + tail.size() > (size_t)INT32_MAX) return fail(SOBEL4X5_EINVAL, "batch too large for one plan");
     }
+    tiles.insert(tiles.end(), tail.begin(), tail.end());
     p->total = (int32_t)tiles.size();
     hipError_t e;
     if ((e = hipMalloc(&p->d_jobs, sizeof(U8Job) * p->count)) != hipSuccess ||

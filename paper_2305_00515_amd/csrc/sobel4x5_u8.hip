@@ -49,6 +49,15 @@ namespace s4x5 {
 namespace {
 
 typedef short v2s __attribute__((ext_vector_type(2)));
+
+// Image and output accesses go through global-address-space pointers.  A
+// pointer read from memory (the batched job table) is otherwise a generic
+// pointer, accessed with FLAT instructions, which count in both vmcnt and
+// lgkmcnt and may complete out of order: every wait for one becomes a full
+// drain of the row prefetch.
+#define GMEM __attribute__((address_space(1)))
+typedef unsigned int gv4u __attribute__((ext_vector_type(4)));
+typedef unsigned int gv2u __attribute__((ext_vector_type(2)));
 typedef unsigned int u32;
 
 __device__ __forceinline__ v2s S2(u32 v) { return __builtin_bit_cast(v2s, v); }
@@ -221,16 +230,16 @@ struct RawRow {
 
 // Issue the loads of one row (fast path: 16-byte aligned rows).
 template <int PPL>
-__device__ __forceinline__ void load_row(RawRow<PPL> &r, const uint8_t *rowp, unsigned ldx, unsigned hx)
+__device__ __forceinline__ void load_row(RawRow<PPL> &r, const GMEM uint8_t *rowp, unsigned ldx, unsigned hx)
 {
     if constexpr (PPL == 16) {
-        uint4 v = *reinterpret_cast<const uint4 *>(rowp + ldx);
+        const gv4u v = *reinterpret_cast<const GMEM gv4u *>(rowp + ldx);
         r.d[0] = v.x; r.d[1] = v.y; r.d[2] = v.z; r.d[3] = v.w;
     } else {
-        uint2 v = *reinterpret_cast<const uint2 *>(rowp + ldx);
+        const gv2u v = *reinterpret_cast<const GMEM gv2u *>(rowp + ldx);
         r.d[0] = v.x; r.d[1] = v.y;
     }
-    r.hw = *reinterpret_cast<const u32 *>(rowp + hx);
+    r.hw = *reinterpret_cast<const GMEM u32 *>(rowp + hx);
 }
 
 // Turn a loaded row into the lane's window: border fix-ups, then DPP halo.
@@ -302,7 +311,7 @@ __device__ __forceinline__ void apply_edge(RawRow<PPL> &r, const EdgeFix &e)
 // Slow path for rows that are not 16-byte aligned: every window byte is read
 // on its own at its clamped column.
 template <int PPL>
-__device__ __forceinline__ Win<PPL> load_row_bytes(const uint8_t *rowp, int xo, int W)
+__device__ __forceinline__ Win<PPL> load_row_bytes(const GMEM uint8_t *rowp, int xo, int W)
 {
     Win<PPL> w;
     auto px = [&](int x) -> u32 { return rowp[x < 0 ? 0 : (x >= W ? W - 1 : x)]; };
@@ -349,12 +358,12 @@ __device__ __forceinline__ void store_row(const U8Job &J, int yo, int xo, bool r
             out[ql >> 2] = __builtin_amdgcn_cvt_pk_u8_f32(fl, ql & 3, (ql & 3) ? out[ql >> 2] : __builtin_bit_cast(u32, fl));
             out[qh >> 2] = __builtin_amdgcn_cvt_pk_u8_f32(fh, qh & 3, (qh & 3) ? out[qh >> 2] : __builtin_bit_cast(u32, fh));
         }
-        uint8_t *p = (J.mag + (int64_t)yo * J.mag_pitch) + (unsigned)xo;
+        GMEM uint8_t *p = ((GMEM uint8_t *)J.mag + (int64_t)yo * J.mag_pitch) + (unsigned)xo;
         if (FAST || (full && J.mag_vec)) {
             if constexpr (PPL == 16)
-                *reinterpret_cast<uint4 *>(p) = make_uint4(out[0], out[1], out[2], out[3]);
+                *reinterpret_cast<GMEM gv4u *>(p) = gv4u{out[0], out[1], out[2], out[3]};
             else
-                *reinterpret_cast<uint2 *>(p) = make_uint2(out[0], out[1]);
+                *reinterpret_cast<GMEM gv2u *>(p) = gv2u{out[0], out[1]};
         } else {
 #pragma unroll
             for (int q = 0; q < PPL; ++q)
@@ -373,7 +382,7 @@ __device__ __forceinline__ void store_row(const U8Job &J, int yo, int xo, bool r
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            char *base = static_cast<char *>(J.dir[k]) + (int64_t)yo * J.dir_pitch;
+            GMEM char *base = (GMEM char *)J.dir[k] + (int64_t)yo * J.dir_pitch;
             if (J.dir_type == 1) {
                 u32 o[NP];   // int16 pixels (2m, 2m+1)
 #pragma unroll
@@ -382,11 +391,11 @@ __device__ __forceinline__ void store_row(const U8Job &J, int yo, int xo, bool r
                     o[m] = a < NP ? perm(U2(P[k][a + 1]), U2(P[k][a]), 0x05040100u)
                                   : perm(U2(P[k][a - NP + 1]), U2(P[k][a - NP]), 0x07060302u);
                 }
-                int16_t *p = reinterpret_cast<int16_t *>(base) + xo;
+                GMEM int16_t *p = reinterpret_cast<GMEM int16_t *>(base) + xo;
                 if (FAST || (full && J.dir_vec)) {
 #pragma unroll
                     for (int m = 0; m < NP; m += 4)
-                        *reinterpret_cast<uint4 *>(p + 2 * m) = make_uint4(o[m], o[m + 1], o[m + 2], o[m + 3]);
+                        *reinterpret_cast<GMEM gv4u *>(p + 2 * m) = gv4u{o[m], o[m + 1], o[m + 2], o[m + 3]};
                 } else {
 #pragma unroll
                     for (int q = 0; q < PPL; ++q)
@@ -399,11 +408,11 @@ __device__ __forceinline__ void store_row(const U8Job &J, int yo, int xo, bool r
                     o[j] = P[k][j].x;
                     o[j + NP] = P[k][j].y;
                 }
-                int32_t *p = reinterpret_cast<int32_t *>(base) + xo;
+                GMEM int32_t *p = reinterpret_cast<GMEM int32_t *>(base) + xo;
                 if (FAST || (full && J.dir_vec)) {
 #pragma unroll
                     for (int q = 0; q < PPL; q += 4)
-                        *reinterpret_cast<int4 *>(p + q) = make_int4(o[q], o[q + 1], o[q + 2], o[q + 3]);
+                        *reinterpret_cast<GMEM gv4u *>(p + q) = gv4u{(u32)o[q], (u32)o[q + 1], (u32)o[q + 2], (u32)o[q + 3]};
                 } else {
 #pragma unroll
                     for (int q = 0; q < PPL; ++q)
@@ -415,6 +424,7 @@ __device__ __forceinline__ void store_row(const U8Job &J, int yo, int xo, bool r
 }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
 
 // What one wave sweeps: per lane the output column xo of its first pixel,
 // per 16-lane group the first output row yo0 and its row count nrow (0 for
@@ -447,7 +457,7 @@ __device__ void sweep(const U8Job &J, const Sweep &g)
     const bool fix_left = FAST ? false : g.fix_left;
     const EdgeFix efix = edge_fix<PPL, OFF>(lane16, xo, W, EDGE && g.fix_left, EDGE && g.fix_right);
 
-    const uint8_t *src = J.src;
+    const GMEM uint8_t *src = (const GMEM uint8_t *)J.src;
     const int64_t pitch = J.src_pitch;
     auto rowp = [&](int t) { return src + (int64_t)clampi(yin0 + t, 0, ymax) * pitch; };
 
@@ -589,33 +599,32 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
         sweep<PPL, OFF, ALIGNED, DIR, false, false>(J, g);
 }
 
-// Geometry of one wave-tile of the batched kernel, ti = {image, kind, tx, ty}
-// (built on the host):
+// Geometry of one wave-tile of the batched kernel, ti = {image, kind | rows << 1,
+// tx, y0} (built on the host by batched_tiles):
 //   kind 0: four tiles side by side, tile columns tx .. tx+3 (a complete
-//           strip), rows [ty*th, ty*th + th): every group walks the same rows
-//           and each load instruction covers one contiguous row segment;
-//   kind 1: four tiles of th rows stacked in tile column tx (row blocks
-//           ty .. ty+3), for the columns an image has beyond its last
-//           complete strip.
+//           strip), output rows [y0, y0 + rows): every group walks the same
+//           rows and each load instruction covers one contiguous row segment;
+//   kind 1: four tiles of th rows stacked in tile column tx, starting at
+//           row y0, for the columns an image has beyond its last complete
+//           strip.
 __device__ __forceinline__ Sweep batch_geometry(const U8Job &J, const int4 &ti, int ppl, int th)
 {
     const int tw = 16 * ppl;
     const int grp = (threadIdx.x >> 4) & 3;
     const int lane16 = threadIdx.x & 15;
     Sweep g;
-    if (ti.y == 0) {
+    if ((ti.y & 1) == 0) {
         const int tx = ti.z + grp;
         g.xo = tx * tw + lane16 * ppl;
-        g.yo0 = ti.w * th;
-        g.nrow = min(th, J.Ho - g.yo0);
+        g.yo0 = ti.w;
+        g.nrow = min(ti.y >> 1, J.Ho - g.yo0);
         g.niter = g.nrow;
         g.fix_right = (ti.z + 4) * tw + 4 > J.W;
         g.fix_left = ti.z == 0;
     } else {
-        const int ty = ti.w + grp;
         g.xo = ti.z * tw + lane16 * ppl;
-        g.yo0 = ty * th;
-        g.nrow = ty < J.nty ? min(th, J.Ho - g.yo0) : 0;
+        g.yo0 = ti.w + grp * th;
+        g.nrow = g.yo0 < J.Ho ? min(th, J.Ho - g.yo0) : 0;
         g.niter = max(max(__builtin_amdgcn_readlane(g.nrow, 0), __builtin_amdgcn_readlane(g.nrow, 16)),
                       max(__builtin_amdgcn_readlane(g.nrow, 32), __builtin_amdgcn_readlane(g.nrow, 48)));
         g.fix_right = (ti.z + 1) * tw + 4 > J.W;
@@ -648,7 +657,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_u8_batched(const U8Job *__restr
         // fast: every group has its full rows, every lane's block and output
         // inside the image, vector-aligned output rows
         bool fast;
-        if (ti.y == 0) {
+        if ((ti.y & 1) == 0) {
             fast = ALIGNED && (ti.z + 4) * TW <= J.Wo && J.mag_vec;
         } else {
             const bool full = __builtin_amdgcn_readlane(g.nrow, 0) == TH && __builtin_amdgcn_readlane(g.nrow, 16) == TH &&
@@ -770,13 +779,20 @@ void u8_tile(U8Job &j, const U8Shape &s)
     j.dir_vec = (da & 15u) == 0;
 }
 
-void batched_tiles(const U8Job &j, int32_t img, std::vector<int4> &out)
+void batched_tiles(const U8Job &j, int32_t img, int th, std::vector<int4> &first, std::vector<int4> &last)
 {
-    const int strips = j.ntx / 4;
-    for (int ty = 0; ty < j.nty; ++ty)
-        for (int s = 0; s < strips; ++s) out.push_back(make_int4(img, 0, 4 * s, ty));
+    // side-by-side strips: the top three quarters of the rows (rounded down
+    // to whole tall chunks of 4 th rows) in tall chunks, the rest in chunks
+    // of th rows, queued after every tall chunk of the batch
+    const int strips = j.ntx / 4, tall = 4 * th;
+    const int htall = (j.Ho - j.Ho / 4) / tall * tall;
+    for (int y = 0; y < htall; y += tall)
+        for (int s = 0; s < strips; ++s) first.push_back(make_int4(img, tall << 1, 4 * s, y));
+    for (int y = htall; y < j.Ho; y += th)
+        for (int s = 0; s < strips; ++s) last.push_back(make_int4(img, th << 1, 4 * s, y));
+    // remaining tile columns: four row blocks stacked
     for (int tx = 4 * strips; tx < j.ntx; ++tx)
-        for (int ty = 0; ty < j.nty; ty += 4) out.push_back(make_int4(img, 1, tx, ty));
+        for (int y = 0; y < j.Ho; y += 4 * th) first.push_back(make_int4(img, 1, tx, y));
 }
 
 hipError_t launch_u8_single(const U8Job &j, int border_valid, const U8Shape &s, hipStream_t st)
