@@ -14,9 +14,10 @@
  *     caller.  Nothing here frees them.  Descriptor arrays and the outputs
  *     struct are HOST memory, read during the call only.
  *   - Pitches and strides are in BYTES.  A row pitch must be at least the
- *     row's width in bytes; any larger value is accepted.  Aligned rows
- *     (16-byte base and pitch) take the fast path; anything else takes a
- *     slower path with identical results.
+ *     row's width in bytes; any larger value is accepted.  Input images
+ *     with 16-byte aligned rows (base and pitch) take the fast path; any
+ *     other input takes a slower path with identical results.  Output rows
+ *     need no alignment.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Work is enqueued asynchronously on it; device faults surface at the
  *     caller's next synchronisation.

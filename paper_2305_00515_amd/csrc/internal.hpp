@@ -27,8 +27,6 @@ struct U8Job {
     int32_t nty;           // tile rows
     int32_t nwt;           // wave tiles, 4 tiles stacked per wave = ntx * nty4
     int32_t nwt_h;         // wave tiles, 4 tiles side by side = ceil(ntx / 4) * nty
-    int32_t mag_vec;       // mag rows 16-byte aligned: vector stores allowed
-    int32_t dir_vec;       // dir rows 16-byte aligned
 };
 
 // Tile shape.  A 16-lane group owns a tile of (16 * ppl) columns x th rows;

@@ -480,7 +480,7 @@ int plan_autotune(sobel4x5_plan_s *p)
     if (int rc = batch_fingerprint(p, want)) return rc;
 
     U8Shape best = ref;
-    double best_ms = time_plan(p, 3);
+    double best_ms = time_plan(p, 10);
     const int ppls[] = {8, 16};
     const int ths[] = {8, 16, 32, 64, 128};
     for (int ppl : ppls)
@@ -497,7 +497,7 @@ int plan_autotune(sobel4x5_plan_s *p)
             if (plan_direct_launch(p, nullptr) != SOBEL4X5_OK) continue;
             if (hipDeviceSynchronize() != hipSuccess) return fail(SOBEL4X5_EHIP, "autotune candidate run failed");
             if (batch_fingerprint(p, got) != SOBEL4X5_OK || got != want) continue;   // never trust a mismatch
-            const double ms = time_plan(p, 3);
+            const double ms = time_plan(p, 10);
             if (ms > 0 && ms < best_ms) {
                 best_ms = ms;
                 best = c;

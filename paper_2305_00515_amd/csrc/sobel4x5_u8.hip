@@ -58,6 +58,11 @@ typedef short v2s __attribute__((ext_vector_type(2)));
 #define GMEM __attribute__((address_space(1)))
 typedef unsigned int gv4u __attribute__((ext_vector_type(4)));
 typedef unsigned int gv2u __attribute__((ext_vector_type(2)));
+// Output rows need no alignment: the HSA runtime runs the GPU in unaligned
+// access mode, so a 16-byte store at any byte address is one
+// global_store_dwordx4 that writes exactly those 16 bytes.
+typedef gv4u gv4u_u __attribute__((aligned(1)));
+typedef gv2u gv2u_u __attribute__((aligned(1)));
 typedef unsigned int u32;
 
 __device__ __forceinline__ v2s S2(u32 v) { return __builtin_bit_cast(v2s, v); }
@@ -359,11 +364,11 @@ __device__ __forceinline__ void store_row(const U8Job &J, int yo, int xo, bool r
             out[qh >> 2] = __builtin_amdgcn_cvt_pk_u8_f32(fh, qh & 3, (qh & 3) ? out[qh >> 2] : __builtin_bit_cast(u32, fh));
         }
         GMEM uint8_t *p = ((GMEM uint8_t *)J.mag + (int64_t)yo * J.mag_pitch) + (unsigned)xo;
-        if (FAST || (full && J.mag_vec)) {
+        if (FAST || full) {
             if constexpr (PPL == 16)
-                *reinterpret_cast<GMEM gv4u *>(p) = gv4u{out[0], out[1], out[2], out[3]};
+                *reinterpret_cast<GMEM gv4u_u *>(p) = gv4u{out[0], out[1], out[2], out[3]};
             else
-                *reinterpret_cast<GMEM gv2u *>(p) = gv2u{out[0], out[1]};
+                *reinterpret_cast<GMEM gv2u_u *>(p) = gv2u{out[0], out[1]};
         } else {
 #pragma unroll
             for (int q = 0; q < PPL; ++q)
@@ -392,10 +397,10 @@ __device__ __forceinline__ void store_row(const U8Job &J, int yo, int xo, bool r
                                   : perm(U2(P[k][a - NP + 1]), U2(P[k][a - NP]), 0x07060302u);
                 }
                 GMEM int16_t *p = reinterpret_cast<GMEM int16_t *>(base) + xo;
-                if (FAST || (full && J.dir_vec)) {
+                if (FAST || full) {
 #pragma unroll
                     for (int m = 0; m < NP; m += 4)
-                        *reinterpret_cast<GMEM gv4u *>(p + 2 * m) = gv4u{o[m], o[m + 1], o[m + 2], o[m + 3]};
+                        *reinterpret_cast<GMEM gv4u_u *>(p + 2 * m) = gv4u{o[m], o[m + 1], o[m + 2], o[m + 3]};
                 } else {
 #pragma unroll
                     for (int q = 0; q < PPL; ++q)
@@ -409,10 +414,10 @@ __device__ __forceinline__ void store_row(const U8Job &J, int yo, int xo, bool r
                     o[j + NP] = P[k][j].y;
                 }
                 GMEM int32_t *p = reinterpret_cast<GMEM int32_t *>(base) + xo;
-                if (FAST || (full && J.dir_vec)) {
+                if (FAST || full) {
 #pragma unroll
                     for (int q = 0; q < PPL; q += 4)
-                        *reinterpret_cast<GMEM gv4u *>(p + q) = gv4u{(u32)o[q], (u32)o[q + 1], (u32)o[q + 2], (u32)o[q + 3]};
+                        *reinterpret_cast<GMEM gv4u_u *>(p + q) = gv4u{(u32)o[q], (u32)o[q + 1], (u32)o[q + 2], (u32)o[q + 3]};
                 } else {
 #pragma unroll
                     for (int q = 0; q < PPL; ++q)
@@ -435,8 +440,9 @@ struct Sweep {
     bool fix_right, fix_left;
 };
 
-// Sweep the wave's tiles top to bottom.  FAST: an interior wave (no border
-// fix-ups, every group active for all niter rows, aligned rows and outputs):
+// Sweep the wave's tiles top to bottom.  FAST: every group active for all
+// niter rows, every lane's block and outputs inside the image, 16-byte
+// aligned input rows (EDGE: with the group-halo fix-ups of an image edge):
 // the loop body has no branches, so the compiler can schedule across steps.
 template <int PPL, int OFF, bool ALIGNED, bool DIR, bool FAST, bool EDGE>
 __device__ void sweep(const U8Job &J, const Sweep &g)
@@ -587,10 +593,9 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
     g.fix_right = (strip * 4 + 4) * TW + 4 > J.W;
     g.fix_left = OFF == 0 && strip == 0;
     // fast: all four tiles complete (every lane's block and output inside
-    // the image) and vector-aligned outputs; the strips at the image edges
-    // take the fast path with mask fix-ups of their group halos
-    const bool fast = ALIGNED && (strip * 4 + 4) * TW <= J.Wo &&
-                      (J.mag == nullptr || J.mag_vec) && (!DIR || J.dir_vec);
+    // the image); the strips at the image edges take the fast path with mask
+    // fix-ups of their group halos
+    const bool fast = ALIGNED && (strip * 4 + 4) * TW <= J.Wo;
     if (fast && !g.fix_right && !g.fix_left)
         sweep<PPL, OFF, ALIGNED, DIR, true, false>(J, g);
     else if (fast)
@@ -655,14 +660,14 @@ __global__ __launch_bounds__(64 * kWaves) void k_u8_batched(const U8Job *__restr
         g.fix_left = g.fix_left && OFF == 0;
         if (g.niter <= 0) continue;
         // fast: every group has its full rows, every lane's block and output
-        // inside the image, vector-aligned output rows
+        // inside the image
         bool fast;
         if ((ti.y & 1) == 0) {
-            fast = ALIGNED && (ti.z + 4) * TW <= J.Wo && J.mag_vec;
+            fast = ALIGNED && (ti.z + 4) * TW <= J.Wo;
         } else {
             const bool full = __builtin_amdgcn_readlane(g.nrow, 0) == TH && __builtin_amdgcn_readlane(g.nrow, 16) == TH &&
                               __builtin_amdgcn_readlane(g.nrow, 32) == TH && __builtin_amdgcn_readlane(g.nrow, 48) == TH;
-            fast = ALIGNED && full && (ti.z + 1) * TW <= J.Wo && J.mag_vec;
+            fast = ALIGNED && full && (ti.z + 1) * TW <= J.Wo;
         }
         if (fast && !g.fix_right && !g.fix_left)
             sweep<PPL, OFF, ALIGNED, false, true, false>(J, g);
@@ -773,10 +778,6 @@ void u8_tile(U8Job &j, const U8Shape &s)
     j.nty4 = (j.nty + 3) / 4;
     j.nwt = j.ntx * j.nty4;
     j.nwt_h = ((j.ntx + 3) / 4) * j.nty;
-    j.mag_vec = ((reinterpret_cast<uintptr_t>(j.mag) | (uintptr_t)j.mag_pitch) & 15u) == 0;
-    uintptr_t da = (uintptr_t)j.dir_pitch;
-    for (int k = 0; k < 4; ++k) da |= reinterpret_cast<uintptr_t>(j.dir[k]);
-    j.dir_vec = (da & 15u) == 0;
 }
 
 void batched_tiles(const U8Job &j, int32_t img, int th, std::vector<int4> &first, std::vector<int4> &last)

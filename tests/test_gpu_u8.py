@@ -200,3 +200,19 @@ def test_edge_strip_widths(oracle_mod, sobel_lib, gpu, w):
     # low amplitude: unsaturated magnitudes near the edges
     low = (img % 3).astype(np.uint8)
     check(oracle_mod, sobel_lib, low, gpu, 0, 0, pitch=p, mag_pitch=p)
+
+
+@pytest.mark.parametrize("w,extra", [(1024, 1), (1024, 3), (2048, 5), (515, 7)])
+def test_fast_path_unaligned_outputs(oracle_mod, sobel_lib, gpu, w, extra):
+    """Aligned input rows with output rows at any byte alignment: the fast
+    path stores whole 16-byte (or 8-byte) vectors at unaligned addresses; the
+    bytes between output rows must keep their sentinel."""
+    h = 40
+    img = synth.rect_image(h, w, 7 * w + extra)
+    mag, _, flat = run(sobel_lib, img, gpu, 0, 0, pitch=synth.round_up(w, 16), mag_pitch=w + extra)
+    om, _ = oracle_mod.sobel_u8(img, 0)
+    assert np.array_equal(mag, om)
+    f = flat.cpu().numpy()
+    pad = np.stack([f[r * (w + extra) + w: (r + 1) * (w + extra)] for r in range(h)])
+    assert (pad == 0x5A).all(), "bytes between output rows were written"
+    assert (f[h * (w + extra):] == 0x5A).all(), "bytes after the last row were written"
