@@ -197,9 +197,10 @@ int sobel4x5_debug_round_mag(const int32_t *S, uint8_t *out, int64_t n, void *st
 
 /*
  * Diagnostic: plain device-to-device copy of nbytes (a multiple of 16;
- * 16-byte aligned device pointers), the same 128-bit streaming access the
- * stencil uses.  It is the measured reference for the achievable HBM
- * bandwidth and the calibration of memory-traffic counters.
+ * 16-byte aligned device pointers) with 128-bit accesses, each workgroup
+ * copying one contiguous 16 KiB block.  It is the measured reference for
+ * the achievable HBM bandwidth and the calibration of memory-traffic
+ * counters.
  */
 int sobel4x5_debug_copy(const void *src, void *dst, int64_t nbytes, void *stream);
 

@@ -19,11 +19,13 @@
 // that edge.
 //
 // Layout of the work: a wave owns a strip of columns and a range of rows of
-// one image.  Each lane holds one column and walks down the rows, keeping
-// five-row rings of every stage in registers; the horizontal taps (+-1, +-2
-// columns) come from the neighbouring lanes by wave-wide DPP shifts.  A wave
-// loads 64 columns and keeps the ones whose whole stencil chain lies inside
-// its lanes (forward: 2 lanes of halo per side, adjoint: 6).
+// one image.  Each lane holds two adjacent columns and walks down the rows,
+// keeping five-row rings of every stage in registers; the horizontal taps
+// (+-1, +-2 columns) are the lane's other column or come from the
+// neighbouring lanes by wave-wide DPP shifts (four shifts give the whole
+// +-2 neighbourhood of a column pair).  A wave loads 128 columns and keeps
+// the ones whose whole stencil chain lies inside its lanes (forward: 2
+// columns of halo per side, adjoint: 6).
 
 #include "internal.hpp"
 
@@ -36,8 +38,8 @@ namespace s4x5 {
 namespace {
 
 constexpr int kWavesPerGroup = 4;
-constexpr int kHaloF = 2, kOwnF = 64 - 2 * kHaloF;   // forward: 60 columns per wave
-constexpr int kHaloB = 6, kOwnB = 64 - 2 * kHaloB;   // adjoint: 52 columns per wave
+constexpr int kHaloF = 2, kOwnF = 128 - 2 * kHaloF;   // forward: 124 columns per wave
+constexpr int kHaloB = 6, kOwnB = 128 - 2 * kHaloB;   // adjoint: 116 columns per wave
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
@@ -53,14 +55,31 @@ __device__ __forceinline__ float from_left(float v)
     return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
 }
 
-// Row filters of one row across the lanes (Eq. (Fx) and the D term of
-// Eq. (Gd-_fast)): hs = v[+1] - v[-1], hr = (v[+2] - v[-2]) + 2 hs.
-__device__ __forceinline__ void hfilters(float v, float &hr, float &hs)
+// A lane's two adjacent columns (a = even offset, b = the next column).
+struct F2 {
+    float a, b;
+};
+__device__ __forceinline__ F2 operator+(F2 x, F2 y) { return {x.a + y.a, x.b + y.b}; }
+__device__ __forceinline__ F2 operator-(F2 x, F2 y) { return {x.a - y.a, x.b - y.b}; }
+__device__ __forceinline__ F2 operator*(float k, F2 x) { return {k * x.a, k * x.b}; }
+
+// The +-1 and +-2 column neighbours of a pair.
+struct Nb {
+    F2 m2, m1, p1, p2;
+};
+__device__ __forceinline__ Nb neighbours(F2 v)
 {
-    const float p1 = from_right(v), m1 = from_left(v);
-    const float p2 = from_right(p1), m2 = from_left(m1);
-    hs = p1 - m1;
-    hr = (p2 - m2) + 2.0f * hs;
+    const float la = from_left(v.a), lb = from_left(v.b), ra = from_right(v.a), rb = from_right(v.b);
+    return {{la, lb}, {lb, v.a}, {v.b, ra}, {ra, rb}};
+}
+
+// Row filters across the columns (Eq. (Fx) and the D term of
+// Eq. (Gd-_fast)): hs = v[+1] - v[-1], hr = (v[+2] - v[-2]) + 2 hs.
+__device__ __forceinline__ void hfilters(F2 v, F2 &hr, F2 &hs)
+{
+    const Nb n = neighbours(v);
+    hs = n.p1 - n.m1;
+    hr = (n.p2 - n.m2) + 2.0f * hs;
 }
 
 // c = [1,4,6,4,1] and c'/d combination over five values a0..a4, b0..b4:
@@ -75,17 +94,29 @@ __device__ __forceinline__ float comb_cd(float a0, float a1, float a2, float a3,
 {
     return 6.0f * ((a0 + a4) + (a1 + a3)) + 2.0f * a2 - 10.0f * (b0 + b4) + 12.0f * b2;
 }
-
-// Columns-first pair (Gy, Gd+) at this lane's column from the lane's v_r and
-// v_s of the centre row: horizontal combination across lanes.
-__device__ __forceinline__ void hcombine(float vr, float vs, float &C, float &Cd)
+__device__ __forceinline__ F2 comb_c(F2 a0, F2 a1, F2 a2, F2 a3, F2 a4)
 {
-    const float r1 = from_right(vr), l1 = from_left(vr);
-    const float r2 = from_right(r1), l2 = from_left(l1);
-    const float s1 = from_right(vs), t1 = from_left(vs);
-    const float s2 = from_right(s1), t2 = from_left(t1);
-    C = comb_c(l2, l1, vr, r1, r2);
-    Cd = comb_cd(l2, l1, vr, r1, r2, t2, vs, s2);
+    return {comb_c(a0.a, a1.a, a2.a, a3.a, a4.a), comb_c(a0.b, a1.b, a2.b, a3.b, a4.b)};
+}
+__device__ __forceinline__ F2 comb_cd(F2 a0, F2 a1, F2 a2, F2 a3, F2 a4, F2 b0, F2 b2, F2 b4)
+{
+    return {comb_cd(a0.a, a1.a, a2.a, a3.a, a4.a, b0.a, b2.a, b4.a),
+            comb_cd(a0.b, a1.b, a2.b, a3.b, a4.b, b0.b, b2.b, b4.b)};
+}
+
+// Columns-first pair (Gy, Gd+) from the lane's v_r and v_s of the centre
+// row: horizontal combination across the columns.
+__device__ __forceinline__ void hcombine(F2 vr, F2 vs, F2 &C, F2 &Cd)
+{
+    const Nb r = neighbours(vr), t = neighbours(vs);
+    C = comb_c(r.m2, r.m1, vr, r.p1, r.p2);
+    Cd = comb_cd(r.m2, r.m1, vr, r.p1, r.p2, t.m2, vs, t.p2);
+}
+// Only the c_h part (the K_y structure).
+__device__ __forceinline__ F2 hcombine_c(F2 vr)
+{
+    const Nb r = neighbours(vr);
+    return comb_c(r.m2, r.m1, vr, r.p1, r.p2);
 }
 
 __device__ __forceinline__ float sum_sq(float Gx, float Gy, float Gp, float Gm)
@@ -111,10 +142,10 @@ template <int P>
 using Ph = std::integral_constant<int, P>;
 
 // ---------------------------------------------------------------- forward
-// Wave (image b, strip s, chunk k): output columns [s*60, s*60+60), output
-// rows [o0, o1).  Lane l holds output column s*60 - 2 + l (centre column
-// + OFF).  Step t loads input row o0 + OFF - 2 + t and, from t = 4 on,
-// finishes output row o0 + t - 4.
+// Wave (image b, strip s, chunk k): output columns [s*124, s*124+124),
+// output rows [o0, o1).  Lane l holds output columns s*124 - 2 + 2l + {0, 1}
+// (centre columns + OFF).  Step t loads input row o0 + OFF - 2 + t and, from
+// t = 4 on, finishes output row o0 + t - 4.
 template <int OFF>
 __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_fwd(F32Args a, int nstrip, int nchunk)
 {
@@ -126,21 +157,23 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_fwd(F32Args a, int 
     const int o0 = (int)((int64_t)k * a.Ho / nchunk), o1 = (int)((int64_t)(k + 1) * a.Ho / nchunk);
     if (o1 <= o0) return;
     const int lane = threadIdx.x & 63;
-    const int ox = s * kOwnF - kHaloF + lane;
-    const bool keep = lane >= kHaloF && lane < kHaloF + kOwnF && ox < a.Wo;
-    const int xc = clampi(ox + OFF, 0, a.W - 1);
-    const char *src = reinterpret_cast<const char *>(a.src) + (int64_t)b * a.src_bstride + (int64_t)xc * 4;
-    char *dst = reinterpret_cast<char *>(a.out) + (int64_t)b * a.out_bstride + (int64_t)(ox < 0 ? 0 : ox) * 4;
+    const int ox = s * kOwnF - kHaloF + 2 * lane;            // output column of element a
+    const bool in_lane = lane >= kHaloF / 2 && lane < (kHaloF + kOwnF) / 2;
+    const bool keep_a = in_lane && ox < a.Wo, keep_b = in_lane && ox + 1 < a.Wo;
+    const char *src = reinterpret_cast<const char *>(a.src) + (int64_t)b * a.src_bstride;
+    const int64_t xa = (int64_t)clampi(ox + OFF, 0, a.W - 1) * 4, xb = (int64_t)clampi(ox + 1 + OFF, 0, a.W - 1) * 4;
+    char *dst = reinterpret_cast<char *>(a.out) + (int64_t)b * a.out_bstride;
+    const int64_t oa = (int64_t)(ox < 0 ? 0 : ox) * 4;
     const int r0 = o0 + OFF - 2;
     auto ld = [&](int t) {
-        return *reinterpret_cast<const float *>(src + (int64_t)clampi(r0 + t, 0, a.H - 1) * a.src_pitch);
+        const char *row = src + (int64_t)clampi(r0 + t, 0, a.H - 1) * a.src_pitch;
+        return F2{*reinterpret_cast<const float *>(row + xa), *reinterpret_cast<const float *>(row + xb)};
     };
     const int T = o1 - o0 + 4;
 
-    float X[5], HR[5], HS[5];
-    float pf[5];
+    F2 X[5], HR[5], HS[5], pf[5];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) X[i] = HR[i] = HS[i] = pf[i] = 0.f;
+    for (int i = 0; i < 5; ++i) X[i] = HR[i] = HS[i] = pf[i] = F2{0.f, 0.f};
     constexpr int PD = 3;   // rows loaded ahead
 #pragma unroll
     for (int t = 0; t < PD; ++t) pf[t] = ld(t);
@@ -149,17 +182,19 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_fwd(F32Args a, int 
         constexpr int p = decltype(phase)::value;
         constexpr int s0 = (p + 1) % 5, s1 = (p + 2) % 5, s2 = (p + 3) % 5, s3 = (p + 4) % 5, s4 = p;
         pf[(p + PD) % 5] = ld(min(t + PD, T - 1));
-        const float x = pf[p];
+        const F2 x = pf[p];
         X[s4] = x;
         hfilters(x, HR[s4], HS[s4]);
         if (t < 4) return;
-        const float Gx = comb_c(HR[s0], HR[s1], HR[s2], HR[s3], HR[s4]);
-        const float Gm = comb_cd(HR[s0], HR[s1], HR[s2], HR[s3], HR[s4], HS[s0], HS[s2], HS[s4]);
-        const float vs = X[s3] - X[s1];
-        const float vr = (X[s4] - X[s0]) + 2.0f * vs;
-        float Gy, Gp;
+        const F2 Gx = comb_c(HR[s0], HR[s1], HR[s2], HR[s3], HR[s4]);
+        const F2 Gm = comb_cd(HR[s0], HR[s1], HR[s2], HR[s3], HR[s4], HS[s0], HS[s2], HS[s4]);
+        const F2 vs = X[s3] - X[s1];
+        const F2 vr = (X[s4] - X[s0]) + 2.0f * vs;
+        F2 Gy, Gp;
         hcombine(vr, vs, Gy, Gp);
-        if (keep) *reinterpret_cast<float *>(dst + (int64_t)(o0 + t - 4) * a.out_pitch) = mag_of(Gx, Gy, Gp, Gm);
+        float *row = reinterpret_cast<float *>(dst + (int64_t)(o0 + t - 4) * a.out_pitch + oa);
+        if (keep_a) row[0] = mag_of(Gx.a, Gy.a, Gp.a, Gm.a);
+        if (keep_b) row[1] = mag_of(Gx.b, Gy.b, Gp.b, Gm.b);
     };
     for (int t = 0; t < T; t += 5) {
         step(t, Ph<0>{});
@@ -175,10 +210,11 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_fwd(F32Args a, int 
 }
 
 // ---------------------------------------------------------------- adjoint
-// Wave (image b, strip s, chunk k): grad_src columns [s*52, s*52+52), rows
-// [X0, X1).  Lane l holds input column c = s*52 - 6 + l.  Step t loads input
-// row r = X0 - 6 + t; the centre row q = r - 2 gets its weighted planes w;
-// the padded adjoint row p = r - 4 is complete and is folded / stored.
+// Wave (image b, strip s, chunk k): grad_src columns [s*116, s*116+116), rows
+// [X0, X1).  Lane l holds input columns c = s*116 - 6 + 2l + {0, 1}.  Step t
+// loads input row r = X0 - 6 + t; the centre row q = r - 2 gets its weighted
+// planes w; the padded adjoint row p = r - 4 is complete and is folded /
+// stored.
 template <int OFF>
 __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int nstrip, int nchunk)
 {
@@ -190,13 +226,15 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
     const int X0 = (int)((int64_t)k * a.H / nchunk), X1 = (int)((int64_t)(k + 1) * a.H / nchunk);
     if (X1 <= X0) return;
     const int lane = threadIdx.x & 63;
-    const int c = s * kOwnB - kHaloB + lane;                  // input column of the lane
-    const bool keep = lane >= kHaloB && lane < kHaloB + kOwnB && c < a.W;
-    const bool ocol = c - OFF >= 0 && c - OFF < a.Wo;          // an output pixel is centred here
-    const int xc = clampi(c, 0, a.W - 1);
-    const int gc = clampi(c - OFF, 0, a.Wo - 1);
-    const char *src = reinterpret_cast<const char *>(a.src) + (int64_t)b * a.src_bstride + (int64_t)xc * 4;
-    const char *gr = reinterpret_cast<const char *>(a.grad) + (int64_t)b * a.g_bstride + (int64_t)gc * 4;
+    const int c = s * kOwnB - kHaloB + 2 * lane;             // input column of element a
+    const bool in_lane = lane >= kHaloB / 2 && lane < (kHaloB + kOwnB) / 2;
+    const bool keep_a = in_lane && c < a.W, keep_b = in_lane && c + 1 < a.W;
+    // an output pixel is centred on the column
+    const bool oc_a = c - OFF >= 0 && c - OFF < a.Wo, oc_b = c + 1 - OFF >= 0 && c + 1 - OFF < a.Wo;
+    const int64_t xa = (int64_t)clampi(c, 0, a.W - 1) * 4, xb = (int64_t)clampi(c + 1, 0, a.W - 1) * 4;
+    const int64_t ga = (int64_t)clampi(c - OFF, 0, a.Wo - 1) * 4, gb = (int64_t)clampi(c + 1 - OFF, 0, a.Wo - 1) * 4;
+    const char *src = reinterpret_cast<const char *>(a.src) + (int64_t)b * a.src_bstride;
+    const char *gr = reinterpret_cast<const char *>(a.grad) + (int64_t)b * a.g_bstride;
     char *dst = reinterpret_cast<char *>(a.out) + (int64_t)b * a.out_bstride + (int64_t)(c < 0 ? 0 : c) * 4;
     const int r0 = X0 - 6;
     const int T = X1 - X0 + 12;
@@ -207,40 +245,45 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
     const bool fold_r = rep && s * kOwnB + kOwnB >= a.W;
 
     auto ldx = [&](int t) {
-        return *reinterpret_cast<const float *>(src + (int64_t)clampi(r0 + t, 0, a.H - 1) * a.src_pitch);
+        const char *row = src + (int64_t)clampi(r0 + t, 0, a.H - 1) * a.src_pitch;
+        return F2{*reinterpret_cast<const float *>(row + xa), *reinterpret_cast<const float *>(row + xb)};
     };
     // grad of the output row whose centre is input row r0 + t - 2 (0 outside)
     auto ldg = [&](int t) {
         const int o = r0 + t - 2 - OFF;
-        float v = 0.f;
-        if (o >= 0 && o < a.Ho) v = *reinterpret_cast<const float *>(gr + (int64_t)o * a.g_pitch);
-        return ocol ? v : 0.f;
+        F2 v{0.f, 0.f};
+        if (o >= 0 && o < a.Ho) {
+            const char *row = gr + (int64_t)o * a.g_pitch;
+            v = F2{*reinterpret_cast<const float *>(row + ga), *reinterpret_cast<const float *>(row + gb)};
+        }
+        return F2{oc_a ? v.a : 0.f, oc_b ? v.b : 0.f};
     };
 
     // rings (slot = step mod 5): input rows, their row filters, centre-row
     // planes w_y, w_p, and the row filters of w_x, w_m
-    float X[5], HR[5], HS[5], WY[5], WP[5], AX[5], AM[5], AS[5];
-    float pfx[5], pfg[5];
+    F2 X[5], HR[5], HS[5], WY[5], WP[5], AX[5], AM[5], AS[5];
+    F2 pfx[5], pfg[5];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) X[i] = HR[i] = HS[i] = WY[i] = WP[i] = AX[i] = AM[i] = AS[i] = pfx[i] = pfg[i] = 0.f;
+    for (int i = 0; i < 5; ++i)
+        X[i] = HR[i] = HS[i] = WY[i] = WP[i] = AX[i] = AM[i] = AS[i] = pfx[i] = pfg[i] = F2{0.f, 0.f};
     constexpr int PD = 3;
 #pragma unroll
     for (int t = 0; t < PD; ++t) {
         pfx[t] = ldx(t);
         pfg[t] = ldg(t);
     }
-    float acc_top = 0.f, acc_bot = 0.f;
+    F2 acc_top{0.f, 0.f}, acc_bot{0.f, 0.f};
 
-    auto store = [&](int row, float v) {
-        if (fold_l) {
-            const float l1 = from_left(v), l2 = from_left(l1);
-            if (c == 0) v += l1 + l2;
+    auto store = [&](int row, F2 v) {
+        if (fold_l || fold_r) {
+            const Nb n = neighbours(v);   // from the row-folded values of every lane
+            if (fold_l && c == 0) v.a += n.m2.a + n.m1.a;                  // columns -2, -1
+            if (fold_r && c == a.W - 1) v.a += n.p1.a + n.p2.a;            // columns W, W+1
+            if (fold_r && c + 1 == a.W - 1) v.b += n.p1.b + n.p2.b;
         }
-        if (fold_r) {
-            const float r1 = from_right(v), r2 = from_right(r1);
-            if (c == a.W - 1) v += r1 + r2;
-        }
-        if (keep) *reinterpret_cast<float *>(dst + (int64_t)row * a.out_pitch) = v;
+        float *p = reinterpret_cast<float *>(dst + (int64_t)row * a.out_pitch);
+        if (keep_a) p[0] = v.a;
+        if (keep_b) p[1] = v.b;
     };
 
     auto step = [&](int t, auto phase) {
@@ -249,36 +292,38 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
         constexpr int s0 = (p + 1) % 5, s1 = (p + 2) % 5, s2 = (p + 3) % 5, s3 = (p + 4) % 5, s4 = p;
         pfx[(p + PD) % 5] = ldx(min(t + PD, T - 1));
         pfg[(p + PD) % 5] = ldg(min(t + PD, T - 1));
-        const float x = pfx[p];
+        const F2 x = pfx[p];
         X[s4] = x;
         hfilters(x, HR[s4], HS[s4]);
         // centre row q = r - 2 (slot s2 of the input rings)
-        const float Gx = comb_c(HR[s0], HR[s1], HR[s2], HR[s3], HR[s4]);
-        const float Gm = comb_cd(HR[s0], HR[s1], HR[s2], HR[s3], HR[s4], HS[s0], HS[s2], HS[s4]);
-        const float vs = X[s3] - X[s1];
-        const float vr = (X[s4] - X[s0]) + 2.0f * vs;
-        float Gy, Gp;
+        const F2 Gx = comb_c(HR[s0], HR[s1], HR[s2], HR[s3], HR[s4]);
+        const F2 Gm = comb_cd(HR[s0], HR[s1], HR[s2], HR[s3], HR[s4], HS[s0], HS[s2], HS[s4]);
+        const F2 vs = X[s3] - X[s1];
+        const F2 vr = (X[s4] - X[s0]) + 2.0f * vs;
+        F2 Gy, Gp;
         hcombine(vr, vs, Gy, Gp);
-        const float gq = pfg[p];                 // grad of the output row centred on q
-        const float sc = scale_of(gq, sum_sq(Gx, Gy, Gp, Gm));
-        const float wx = sc * Gx, wy = sc * Gy, wp = 0.5f * sc * Gp, wm = 0.5f * sc * Gm;
+        const F2 gq = pfg[p];                    // grad of the output row centred on q
+        const F2 sc{scale_of(gq.a, sum_sq(Gx.a, Gy.a, Gp.a, Gm.a)), scale_of(gq.b, sum_sq(Gx.b, Gy.b, Gp.b, Gm.b))};
+        const F2 wx{sc.a * Gx.a, sc.b * Gx.b}, wy{sc.a * Gy.a, sc.b * Gy.b};
+        const F2 wp{0.5f * sc.a * Gp.a, 0.5f * sc.b * Gp.b}, wm{0.5f * sc.a * Gm.a, 0.5f * sc.b * Gm.b};
         // w rings hold centre rows q-4 .. q in slots (p+1)%5 .. p as well
         WY[s4] = wy;
         WP[s4] = wp;
-        float hs_x;   // (only h_r of w_x enters K_x)
+        F2 hs_x;   // (only h_r of w_x enters K_x)
         hfilters(wx, AX[s4], hs_x);
         hfilters(wm, AM[s4], AS[s4]);
-        // padded adjoint row p_ = q - 2 (slot s2 of the w rings)
-        const float A = comb_c(AX[s0], AX[s1], AX[s2], AX[s3], AX[s4]) +
-                        comb_cd(AM[s0], AM[s1], AM[s2], AM[s3], AM[s4], AS[s0], AS[s2], AS[s4]);
-        const float vsy = WY[s3] - WY[s1];
-        const float vry = (WY[s4] - WY[s0]) + 2.0f * vsy;
-        const float vsp = WP[s3] - WP[s1];
-        const float vrp = (WP[s4] - WP[s0]) + 2.0f * vsp;
-        float By, By_d, Bp_c, Bp;   // K_y * w_y = c_h(v_r); K_d+ * w_p = c'_h(v_r) - d_h(v_s)
-        hcombine(vry, vsy, By, By_d);
+        // padded adjoint row p_ = q - 2 (slot s2 of the w rings):
+        // K_x * w_x + K_d- * w_m (rows first) + K_y * w_y + K_d+ * w_p (columns first)
+        const F2 A = comb_c(AX[s0], AX[s1], AX[s2], AX[s3], AX[s4]) +
+                     comb_cd(AM[s0], AM[s1], AM[s2], AM[s3], AM[s4], AS[s0], AS[s2], AS[s4]);
+        const F2 vsy = WY[s3] - WY[s1];
+        const F2 vry = (WY[s4] - WY[s0]) + 2.0f * vsy;
+        const F2 vsp = WP[s3] - WP[s1];
+        const F2 vrp = (WP[s4] - WP[s0]) + 2.0f * vsp;
+        const F2 By = hcombine_c(vry);
+        F2 Bp_c, Bp;
         hcombine(vrp, vsp, Bp_c, Bp);
-        const float P = -(A + By + Bp);
+        const F2 P = F2{0.f, 0.f} - (A + By + Bp);
         const int pr = r0 + t - 4;               // padded row of P
         if (pr < X0 - 2 || pr >= X1 + 2) return;  // warm-up and rows of other waves
         if (!rep) {
@@ -286,13 +331,13 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
             return;
         }
         if (pr < 0) {
-            acc_top += P;
+            acc_top = acc_top + P;
         } else if (pr >= a.H) {
-            acc_bot += P;
+            acc_bot = acc_bot + P;
             if (pr == a.H + 1) store(a.H - 1, acc_bot);
         } else if (pr >= X0 && pr < X1) {
-            float v = P;
-            if (pr == 0) v += acc_top;
+            F2 v = P;
+            if (pr == 0) v = v + acc_top;
             if (pr == a.H - 1)
                 acc_bot = v;
             else
