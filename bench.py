@@ -44,12 +44,12 @@ def parse():
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--only", default=None,
-                   help="comma-separated subset of: u8, copy, sweep, batched, f32")
+                   help="comma-separated subset of: u8, copy, sweep, batched, f32, weighted")
     p.add_argument("--no-cpu-baseline", action="store_true")
     a = p.parse_args()
     if a.only is not None:
         a.only = set(x.strip() for x in a.only.split(",") if x.strip())
-        bad = a.only - {"u8", "copy", "sweep", "batched", "f32"}
+        bad = a.only - {"u8", "copy", "sweep", "batched", "f32", "weighted"}
         if bad:
             p.error("unknown --only part(s): %s" % ", ".join(sorted(bad)))
     return a
@@ -192,6 +192,23 @@ def bench_f32(torch, api, synth, dev, steps, warmup):
     return res
 
 
+def bench_weighted(torch, api, synth, dev, steps, warmup):
+    """Run-time weights (the family K(a, b, n, m) at (1, 3, 5, 10)) on the
+    8192x8192 image, magnitude only, rotating buffers as in the headline."""
+    img = synth.rect_image(N, N, 3)
+    nsets = max(2, ROTATE_BYTES // (2 * N * N))
+    srcs, mags = image_sets(torch, img, dev, nsets)
+    w = api.family_weights(*api.family_products(1, 3, 5, 10))
+    k = max(10, steps // 4)
+    ms = time_launches(torch, lambda i: api.sobel4x5_u8_weighted(srcs[i % nsets], w, mag=mags[i % nsets]), k,
+                       max(3, warmup // 4))
+    del srcs, mags
+    torch.cuda.empty_cache()
+    px = N * N
+    return {"weights": "K(a,b,n,m) at (1,3,5,10)", "ms": round(ms, 5), "gpx_per_s": round(px / (ms * 1e-3) / 1e9, 2),
+            "hbm_frac": round(2 * px / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def bench_copy(torch, api, dev, steps):
     """Achievable streaming bandwidth: a plain 128-bit copy of 1 GiB (2 GiB moved)."""
     n = 1 << 30
@@ -300,6 +317,9 @@ def main():
     if want("batched"):
         log("batched 256 images")
         line["batched"] = bench_batched(torch, api, synth, dev, args.steps, args.warmup)
+    if want("weighted"):
+        log("run-time weights 8192x8192")
+        line["weighted"] = bench_weighted(torch, api, synth, dev, args.steps, args.warmup)
     if want("f32"):
         log("fp32 32x1024^2 fwd+bwd")
         line["f32"] = bench_f32(torch, api, synth, dev, args.steps, args.warmup)

@@ -98,6 +98,43 @@ int sobel4x5_validate_u8(const uint8_t *src, int32_t width, int32_t height, int6
                          int32_t border, const sobel4x5_outputs *out);
 
 /*
+ * Generalised weights (Sec. 3.2, Eq. (sobel5_param)).
+ *
+ * sobel4x5_u8_weighted -- sobel4x5_u8 with run-time integer kernels.
+ *   weights : HOST array of 4*25 int32: four 5x5 kernels in plane order
+ *             (0 deg, 45 deg, 90 deg, 135 deg), each row-major; tap (i, j)
+ *             multiplies the pixel at offset (i-2, j-2) (correlation, as for
+ *             the default operator).  Read during the call only.
+ *   Every kernel must be antisymmetric under a half turn
+ *   (k[4-i][4-j] == -k[i][j], so k[2][2] == 0; the family K(a, b, n, m) is)
+ *   and have sum |k_ij| <= 32768 (then |G| < 2^23 and int32 planes are
+ *   exact); with dir_type DIR_S16, sum |k_ij| <= 128 (|G| <= 32767).
+ *   Anything else is SOBEL4X5_EINVAL.  Other arguments, outputs and the
+ *   uint8 rounding min(255, round(sqrt(S))) are as for sobel4x5_u8.  The
+ *   default weights of Eq. (sobel5_1) give the same results as sobel4x5_u8,
+ *   which runs them on a faster path.
+ */
+int sobel4x5_u8_weighted(const uint8_t *src, int32_t width, int32_t height, int64_t src_pitch,
+                         int32_t border, const int32_t *weights, const sobel4x5_outputs *out,
+                         void *stream);
+
+/* Host-only check of a weights array for sobel4x5_u8_weighted with the
+ * given dir_type (never touches the GPU). */
+int sobel4x5_validate_weights(const int32_t *weights, int32_t dir_type);
+
+/*
+ * sobel4x5_family_weights -- the four kernels of the family K(a, b, n, m)
+ * of Eq. (sobel5_param) (K_x, K_d, K_y = K_x transposed, K_dt = K_d mirrored
+ * left-right), written to weights_out (HOST, 4*25 int32, the layout of
+ * sobel4x5_u8_weighted).  The family is given by its six distinct integer
+ * weights a, a*b, a*n, a*m, a*n*b, a*m*b, which must be positive and
+ * consistent: (a*n)(a*b) == a(a*n*b) and (a*m)(a*b) == a(a*m*b).
+ * Eq. (sobel5_1) is (1, 2, 4, 6, 8, 12).  EINVAL otherwise.
+ */
+int sobel4x5_family_weights(int32_t a, int32_t ab, int32_t an, int32_t am, int32_t anb, int32_t amb,
+                            int32_t *weights_out);
+
+/*
  * Batched uint8 magnitudes: many images of uneven sizes in ONE launch of a
  * persistent work-queue kernel (not in the paper; it applies the same integer
  * arithmetic per image).

@@ -12,6 +12,8 @@ import ctypes
 import os
 from pathlib import Path
 
+import numpy as np
+
 import torch
 
 _PKG = Path(__file__).resolve().parent
@@ -65,6 +67,9 @@ def _load() -> ctypes.CDLL:
         "sobel4x5_f32_fwd": [P, I32, I32, I32, I64, I64, I32, P, I64, I64, P],
         "sobel4x5_f32_bwd": [P, I64, I64, P, I64, I64, I32, I32, I32, I32, P, I64, I64, P],
         "sobel4x5_validate_f32": [P, I32, I32, I32, I64, I64, I32, P, I64, I64],
+        "sobel4x5_u8_weighted": [P, I32, I32, I64, I32, P, ctypes.POINTER(Outputs), P],
+        "sobel4x5_validate_weights": [P, I32],
+        "sobel4x5_family_weights": [I32] * 6 + [P],
         "sobel4x5_debug_round_mag": [P, P, I64, P],
         "sobel4x5_debug_copy": [P, P, I64, P],
         "sobel4x5_status_string": [ctypes.c_int],
@@ -110,13 +115,8 @@ def out_shape(h: int, w: int, border: int):
     return (h, w) if border == BORDER_REPLICATE else (h - 4, w - 4)
 
 
-def sobel4x5_u8(src: torch.Tensor, border: int = BORDER_REPLICATE, *, mag: torch.Tensor | None = None,
-                want_mag: bool = True, dir_type: int = DIR_NONE, dirs: list | None = None):
-    """uint8 image (H, W) on the GPU -> (mag uint8 (Ho, Wo) or None, [4 planes] or None).
-
-    Planes are 0 deg Gx, 45 deg Gd, 90 deg Gy, 135 deg Gdt as int16 (DIR_S16)
-    or int32 (DIR_S32).  Output tensors may be passed in (any row pitch).
-    """
+def _u8_outputs(src, border, mag, want_mag, dir_type, dirs):
+    """Outputs struct (and the tensors) for a uint8 call on src."""
     _need_cuda(src, torch.uint8, "src")
     h, w, pitch = _rows(src, "src")
     ho, wo = out_shape(h, w, border)
@@ -146,9 +146,65 @@ def sobel4x5_u8(src: torch.Tensor, border: int = BORDER_REPLICATE, *, mag: torch
             raise ValueError("all four directional planes must share one row pitch")
         out.dir_pitch = pitches.pop()
     out.dir_type = dir_type
+    res = ((mag if (want_mag or out.mag) else None), (dirs if dir_type != DIR_NONE else None))
+    return out, (h, w, pitch), res
+
+
+def sobel4x5_u8(src: torch.Tensor, border: int = BORDER_REPLICATE, *, mag: torch.Tensor | None = None,
+                want_mag: bool = True, dir_type: int = DIR_NONE, dirs: list | None = None):
+    """uint8 image (H, W) on the GPU -> (mag uint8 (Ho, Wo) or None, [4 planes] or None).
+
+    Planes are 0 deg Gx, 45 deg Gd, 90 deg Gy, 135 deg Gdt as int16 (DIR_S16)
+    or int32 (DIR_S32).  Output tensors may be passed in (any row pitch).
+    """
+    out, (h, w, pitch), res = _u8_outputs(src, border, mag, want_mag, dir_type, dirs)
     _check(lib.sobel4x5_u8(src.data_ptr(), w, h, pitch, border, ctypes.byref(out), _stream(src)),
            "sobel4x5_u8")
-    return (mag if (want_mag or out.mag) else None), (dirs if dir_type != DIR_NONE else None)
+    return res
+
+
+def _weights_buf(weights):
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.int64).reshape(4, 5, 5))
+    if np.abs(w).max() >= 2 ** 31:
+        raise ValueError("weights must fit int32")
+    return np.ascontiguousarray(w.astype(np.int32))
+
+
+def sobel4x5_u8_weighted(src: torch.Tensor, weights, border: int = BORDER_REPLICATE, *,
+                         mag: torch.Tensor | None = None, want_mag: bool = True, dir_type: int = DIR_NONE,
+                         dirs: list | None = None):
+    """sobel4x5_u8 with run-time integer kernels (4, 5, 5), plane order as the
+    default operator; each kernel antisymmetric under a half turn."""
+    wb = _weights_buf(weights)
+    out, (h, w, pitch), res = _u8_outputs(src, border, mag, want_mag, dir_type, dirs)
+    _check(lib.sobel4x5_u8_weighted(src.data_ptr(), w, h, pitch, border, wb.ctypes.data, ctypes.byref(out),
+                                    _stream(src)), "sobel4x5_u8_weighted")
+    return res
+
+
+def validate_weights(weights, dir_type: int = DIR_NONE) -> None:
+    """Raises SobelError unless sobel4x5_u8_weighted accepts these weights."""
+    wb = _weights_buf(weights)
+    _check(lib.sobel4x5_validate_weights(wb.ctypes.data, dir_type), "sobel4x5_validate_weights")
+
+
+def family_weights(a: int, ab: int, an: int, am: int, anb: int, amb: int) -> np.ndarray:
+    """The four kernels (4, 5, 5) of the family K(a, b, n, m), from its six
+    integer weights a, a*b, a*n, a*m, a*n*b, a*m*b."""
+    out = np.zeros((4, 5, 5), dtype=np.int32)
+    _check(lib.sobel4x5_family_weights(a, ab, an, am, anb, amb, out.ctypes.data), "sobel4x5_family_weights")
+    return out
+
+
+def family_products(a, b, n, m):
+    """(a, a*b, a*n, a*m, a*n*b, a*m*b) for parameters given as ints,
+    fractions or decimal strings; ValueError unless all six are integers."""
+    from fractions import Fraction
+    A, B, N, M = (Fraction(str(v)) if not isinstance(v, Fraction) else v for v in (a, b, n, m))
+    prods = (A, A * B, A * N, A * M, A * N * B, A * M * B)
+    if any(p.denominator != 1 for p in prods):
+        raise ValueError("the family weights must all be integers, got %s" % (tuple(str(p) for p in prods),))
+    return tuple(int(p) for p in prods)
 
 
 def _images(srcs, mags, border):

@@ -71,6 +71,22 @@ void batched_tiles(const U8Job &j, int32_t img, int th, std::vector<int4> &first
 // once for shape `s` (occupancy x CUs), or 0 on error.
 int u8_persistent_grid(const U8Shape &s, int border_valid, bool aligned);
 
+// uint8 operator with run-time weights (four integer kernels that are
+// antisymmetric under a half turn), as coefficients of the 12 upper-half
+// pair differences: coef[plane][t] = k_plane[i_t][j_t] with taps (0,0..4),
+// (1,0..4), (2,0), (2,1).
+struct WJob {
+    const uint8_t *src;
+    uint8_t *mag;          // may be null
+    void *dir[4];          // used iff dir_type != 0
+    int64_t src_pitch, mag_pitch, dir_pitch;
+    int32_t W, H, Wo, Ho;
+    int32_t off;           // 0 replicate, 2 valid
+    int32_t dir_type;      // 0 none, 1 int16, 2 int32
+    int32_t coef[4][12];
+};
+hipError_t launch_u8_weighted(const WJob &j, hipStream_t stream);
+
 hipError_t launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t stream);
 hipError_t launch_round_mag(const int32_t *S, uint8_t *out, int64_t n, hipStream_t stream);
 

@@ -734,6 +734,93 @@ int sobel4x5_f32_bwd(const float *src, int64_t src_pitch, int64_t src_bstride, c
     return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_f32_bwd launch");
 }
 
+int sobel4x5_validate_weights(const int32_t *w, int32_t dir_type)
+{
+    if (!w) return fail(SOBEL4X5_EINVAL, "weights is NULL");
+    const int64_t limit = dir_type == SOBEL4X5_DIR_S16 ? 128 : 32768;
+    for (int k = 0; k < 4; ++k) {
+        const int32_t *K = w + 25 * k;
+        int64_t sum = 0;
+        for (int i = 0; i < 5; ++i)
+            for (int j = 0; j < 5; ++j) {
+                if ((int64_t)K[5 * i + j] != -(int64_t)K[5 * (4 - i) + (4 - j)])
+                    return fail(SOBEL4X5_EINVAL,
+                                "kernel %d is not antisymmetric under a half turn at tap (%d, %d)", k, i, j);
+                sum += K[5 * i + j] < 0 ? -(int64_t)K[5 * i + j] : K[5 * i + j];
+            }
+        if (sum > limit)
+            return fail(SOBEL4X5_EINVAL, "kernel %d: sum of |weights| = %lld exceeds %lld%s", k, (long long)sum,
+                        (long long)limit, dir_type == SOBEL4X5_DIR_S16 ? " (int16 planes)" : "");
+    }
+    return ok();
+}
+
+int sobel4x5_family_weights(int32_t a, int32_t ab, int32_t an, int32_t am, int32_t anb, int32_t amb,
+                            int32_t *out)
+{
+    if (!out) return fail(SOBEL4X5_EINVAL, "weights_out is NULL");
+    if (a <= 0 || ab <= 0 || an <= 0 || am <= 0 || anb <= 0 || amb <= 0)
+        return fail(SOBEL4X5_EINVAL, "the six family weights must be positive");
+    if ((int64_t)an * ab != (int64_t)a * anb || (int64_t)am * ab != (int64_t)a * amb)
+        return fail(SOBEL4X5_EINVAL, "inconsistent family weights: need (a*n)(a*b) = a(a*n*b), (a*m)(a*b) = a(a*m*b)");
+    // K_x = a [1 n m n 1]^T x [-1 -b 0 b 1]; K_y its transpose
+    const int32_t col[5] = {a, an, am, an, a};          // a * [1 n m n 1]
+    const int32_t colb[5] = {ab, anb, amb, anb, ab};    // a * b * [1 n m n 1]
+    int32_t Kx[5][5], Kd[5][5];
+    for (int i = 0; i < 5; ++i) {
+        Kx[i][0] = -col[i];
+        Kx[i][1] = -colb[i];
+        Kx[i][2] = 0;
+        Kx[i][3] = colb[i];
+        Kx[i][4] = col[i];
+    }
+    // K_d as printed in Eq. (sobel5_param)
+    const int32_t d[5][5] = {{-am, -an, -a, -ab, 0},
+                             {-an, -amb, -anb, 0, ab},
+                             {-a, -anb, 0, anb, a},
+                             {-ab, 0, anb, amb, an},
+                             {0, ab, a, an, am}};
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j) Kd[i][j] = d[i][j];
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j) {
+            out[0 * 25 + 5 * i + j] = Kx[i][j];           // 0 deg
+            out[1 * 25 + 5 * i + j] = Kd[i][j];           // 45 deg
+            out[2 * 25 + 5 * i + j] = Kx[j][i];           // 90 deg: transpose
+            out[3 * 25 + 5 * i + j] = Kd[i][4 - j];       // 135 deg: left-right mirror
+        }
+    return ok();
+}
+
+int sobel4x5_u8_weighted(const uint8_t *src, int32_t width, int32_t height, int64_t src_pitch, int32_t border,
+                         const int32_t *weights, const sobel4x5_outputs *out, void *stream)
+{
+    int32_t Wo, Ho;
+    if (int rc = validate_u8(src, width, height, src_pitch, border, out, &Wo, &Ho)) return rc;
+    if (int rc = sobel4x5_validate_weights(weights, out->dir_type)) return rc;
+    WJob j{};
+    j.src = src;
+    j.mag = out->mag;
+    for (int k = 0; k < 4; ++k) j.dir[k] = out->dir_type ? out->dir[k] : nullptr;
+    j.src_pitch = src_pitch;
+    j.mag_pitch = out->mag_pitch;
+    j.dir_pitch = out->dir_pitch;
+    j.W = width;
+    j.H = height;
+    j.Wo = Wo;
+    j.Ho = Ho;
+    j.off = border == SOBEL4X5_BORDER_VALID ? 2 : 0;
+    j.dir_type = out->dir_type;
+    // upper-half taps (0, 0..4), (1, 0..4), (2, 0), (2, 1)
+    for (int k = 0; k < 4; ++k)
+        for (int t = 0; t < 12; ++t) {
+            const int i = t < 5 ? 0 : (t < 10 ? 1 : 2), jj = t < 10 ? t % 5 : t - 10;
+            j.coef[k][t] = weights[25 * k + 5 * i + jj];
+        }
+    hipError_t e = launch_u8_weighted(j, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_u8_weighted launch");
+}
+
 int sobel4x5_debug_copy(const void *src, void *dst, int64_t nbytes, void *stream)
 {
     if (nbytes < 0 || (nbytes % 16) || (nbytes > 0 && (!src || !dst)) ||

@@ -1,0 +1,81 @@
+"""GPU parity of sobel4x5_u8_weighted against the CPU oracle: bit-exact."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2305_00515_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FAMILIES = [(1, 2, 4, 6), (1, 1, 2, 3), (2, Fraction(3, 2), 2, 3), (1, 3, 5, 10)]
+
+
+def antisym_random(rng, amp):
+    """Four random integer 5x5 kernels, antisymmetric under a half turn."""
+    w = rng.integers(-amp, amp + 1, size=(4, 5, 5))
+    return w - w[:, ::-1, ::-1]                      # k - rot180(k): antisymmetric
+
+
+def run(api, img, dev, weights, border, dir_type, pitch=None):
+    h, w = img.shape
+    pitch = w if pitch is None else pitch
+    flat = torch.full(((h - 1) * pitch + w + 64,), 0xA5, dtype=torch.uint8, device=dev)
+    src = flat.as_strided((h, w), (pitch, 1))
+    src.copy_(torch.from_numpy(img))
+    mag, dirs = api.sobel4x5_u8_weighted(src, weights, border, dir_type=dir_type)
+    torch.cuda.synchronize()
+    d = None if dirs is None else np.stack([x.cpu().numpy() for x in dirs]).astype(np.int64)
+    return mag.cpu().numpy(), d
+
+
+@pytest.mark.parametrize("abnm", FAMILIES)
+def test_family_parity(oracle_mod, sobel_lib, gpu, abnm):
+    w = sobel_lib.family_weights(*sobel_lib.family_products(*abnm))
+    dt = sobel_lib.DIR_S16 if np.abs(w).sum(axis=(1, 2)).max() <= 128 else sobel_lib.DIR_S32
+    for (h, wd) in [(97, 301), (5, 5), (1, 7), (64, 1030)]:
+        img = synth.rect_image(h, wd, h * 31 + wd)
+        for border in (0, 1):
+            if border and (h < 5 or wd < 5):
+                continue
+            mag, d = run(sobel_lib, img, gpu, w, border, dt)
+            om, od = oracle_mod.sobel_u8(img, border, weights=w)
+            assert np.array_equal(mag, om), (abnm, h, wd, border)
+            assert np.array_equal(d, od), (abnm, h, wd, border)
+
+
+def test_random_antisymmetric_kernels(oracle_mod, sobel_lib, gpu):
+    rng = np.random.default_rng(11)
+    for trial in range(4):
+        w = antisym_random(rng, 3 + 40 * trial)
+        img = synth.rect_image(70, 211, 500 + trial)
+        low = (img % 4).astype(np.uint8)              # low amplitude: unsaturated magnitudes
+        for im in (img, low):
+            mag, d = run(sobel_lib, im, gpu, w, 0, sobel_lib.DIR_S32, pitch=213)
+            om, od = oracle_mod.sobel_u8(im, 0, weights=w)
+            assert np.array_equal(mag, om) and np.array_equal(d, od), trial
+
+
+def test_default_weights_match_fast_path(sobel_lib, gpu):
+    """The weighted path with Eq. (sobel5_1) equals the packed default path."""
+    img = synth.field_image(300, 1000, 9)
+    src = torch.from_numpy(img).to(gpu)
+    w = sobel_lib.family_weights(1, 2, 4, 6, 8, 12)
+    m1, d1 = sobel_lib.sobel4x5_u8(src, dir_type=sobel_lib.DIR_S16)
+    m2, d2 = sobel_lib.sobel4x5_u8_weighted(src, w, dir_type=sobel_lib.DIR_S16)
+    torch.cuda.synchronize()
+    assert torch.equal(m1, m2)
+    assert all(torch.equal(a, b) for a, b in zip(d1, d2))
+
+
+def test_weighted_rejects_bad_weights(sobel_lib, gpu):
+    src = torch.zeros((16, 16), dtype=torch.uint8, device=gpu)
+    w = sobel_lib.family_weights(1, 2, 4, 6, 8, 12)
+    bad = w.copy()
+    bad[0, 2, 2] = 1                                   # centre tap of an antisymmetric kernel is 0
+    with pytest.raises(sobel_lib.SobelError):
+        sobel_lib.sobel4x5_u8_weighted(src, bad)
+    big = sobel_lib.family_weights(*sobel_lib.family_products(1, 3, 5, 10))
+    with pytest.raises(sobel_lib.SobelError):
+        sobel_lib.sobel4x5_u8_weighted(src, big, dir_type=sobel_lib.DIR_S16)
