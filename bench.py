@@ -44,12 +44,12 @@ def parse():
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--only", default=None,
-                   help="comma-separated subset of: u8, copy, sweep, batched, f32, weighted")
+                   help="comma-separated subset of: u8, copy, sweep, batched, f32, weighted, pipe")
     p.add_argument("--no-cpu-baseline", action="store_true")
     a = p.parse_args()
     if a.only is not None:
         a.only = set(x.strip() for x in a.only.split(",") if x.strip())
-        bad = a.only - {"u8", "copy", "sweep", "batched", "f32", "weighted"}
+        bad = a.only - {"u8", "copy", "sweep", "batched", "f32", "weighted", "pipe"}
         if bad:
             p.error("unknown --only part(s): %s" % ", ".join(sorted(bad)))
     return a
@@ -209,6 +209,34 @@ def bench_weighted(torch, api, synth, dev, steps, warmup):
             "hbm_frac": round(2 * px / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def bench_pipe(torch, api, synth, dev, steps):
+    """Host -> device -> host: 64 images of 3840x2160 in pinned host memory
+    through the pipeline (copies overlapped with kernels over 3 slots),
+    against one slot (copy in, kernel, copy out in sequence)."""
+    h, w, n = 2160, 3840, 64
+    base = [synth.field_image(h, w, 3000 + i) for i in range(4)]
+    srcs = []
+    for i in range(n):
+        t = torch.empty((h, w), dtype=torch.uint8, pin_memory=True)
+        t.copy_(torch.from_numpy(base[i % 4]))
+        srcs.append(t)
+    mags = [torch.empty((h, w), dtype=torch.uint8, pin_memory=True) for _ in range(n)]
+    out = {"images": n, "shape": [h, w], "host_memory": "pinned"}
+    for depth in (1, 3):
+        p = api.Pipe(w, h, depth)
+        p.run(srcs[:4], mags[:4])
+        reps = max(1, steps // 100)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            p.run(srcs, mags)
+        dt = (time.perf_counter() - t0) / reps
+        p.close()
+        out["depth%d" % depth] = {"ms": round(dt * 1e3, 3), "gpx_per_s": round(n * h * w / dt / 1e9, 2),
+                                  "pcie_GBps": round(2 * n * h * w / dt / 1e9, 2)}
+    out["overlap_speedup"] = round(out["depth1"]["ms"] / out["depth3"]["ms"], 3)
+    return out
+
+
 def bench_copy(torch, api, dev, steps):
     """Achievable streaming bandwidth: a plain 128-bit copy of 1 GiB (2 GiB moved)."""
     n = 1 << 30
@@ -320,6 +348,9 @@ def main():
     if want("weighted"):
         log("run-time weights 8192x8192")
         line["weighted"] = bench_weighted(torch, api, synth, dev, args.steps, args.warmup)
+    if want("pipe"):
+        log("host pipeline 64 x 3840x2160")
+        line["pipe"] = bench_pipe(torch, api, synth, dev, args.steps)
     if want("f32"):
         log("fp32 32x1024^2 fwd+bwd")
         line["f32"] = bench_f32(torch, api, synth, dev, args.steps, args.warmup)

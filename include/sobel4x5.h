@@ -191,6 +191,31 @@ int sobel4x5_batched(const sobel4x5_image *imgs, int32_t count, int32_t border, 
 int sobel4x5_validate_batch(const sobel4x5_image *imgs, int32_t count, int32_t border);
 
 /*
+ * Host pipeline: uint8 images in HOST memory -> magnitudes in HOST memory.
+ * The paper measures host<->device transfer as the dominant cost of the
+ * whole operation (Table 1, IO column; Sec. 5) and names overlapping it as
+ * future work (Sec. 6).  A pipeline holds `depth` slots, each with device
+ * buffers for the largest image, pinned staging buffers and a stream of its
+ * own; image i uses slot i % depth, so the copy to the device of one image,
+ * the kernel of another and the copy back of a third run at the same time.
+ *
+ * sobel4x5_pipe_create -- allocate a pipeline for images of at most
+ *   max_width x max_height (device: 2 * depth * round_up(max_width, 256) *
+ *   max_height bytes; pinned host: the same).  depth in [1, 16].
+ * sobel4x5_pipe_run -- process `count` images (sobel4x5_image descriptors
+ *   whose src and mag point to HOST memory, pageable or pinned; pinned
+ *   buffers are copied directly, pageable ones through the staging
+ *   buffers) with the given border; magnitude only.  Synchronous: returns
+ *   when every magnitude is in host memory.  A pipeline must not be run by
+ *   two threads at once.
+ * sobel4x5_pipe_destroy -- wait for nothing, free everything.
+ */
+typedef struct sobel4x5_pipe_s *sobel4x5_pipe;
+int sobel4x5_pipe_create(int32_t max_width, int32_t max_height, int32_t depth, sobel4x5_pipe *out);
+int sobel4x5_pipe_run(sobel4x5_pipe pipe, const sobel4x5_image *host_imgs, int32_t count, int32_t border);
+int sobel4x5_pipe_destroy(sobel4x5_pipe pipe);
+
+/*
  * Real-valued path (not in the paper): the same correlation in fp32 on a
  * batch of images, for use as a differentiable edge loss.
  *

@@ -70,6 +70,9 @@ def _load() -> ctypes.CDLL:
         "sobel4x5_u8_weighted": [P, I32, I32, I64, I32, P, ctypes.POINTER(Outputs), P],
         "sobel4x5_validate_weights": [P, I32],
         "sobel4x5_family_weights": [I32] * 6 + [P],
+        "sobel4x5_pipe_create": [I32, I32, I32, ctypes.POINTER(P)],
+        "sobel4x5_pipe_run": [P, ctypes.POINTER(Image), I32, I32],
+        "sobel4x5_pipe_destroy": [P],
         "sobel4x5_debug_round_mag": [P, P, I64, P],
         "sobel4x5_debug_copy": [P, P, I64, P],
         "sobel4x5_status_string": [ctypes.c_int],
@@ -205,6 +208,62 @@ def family_products(a, b, n, m):
     if any(p.denominator != 1 for p in prods):
         raise ValueError("the family weights must all be integers, got %s" % (tuple(str(p) for p in prods),))
     return tuple(int(p) for p in prods)
+
+
+def _host_rows(a, name):
+    """(height, width, pitch bytes, address) of a 2-D uint8 host array
+    (numpy or CPU tensor, unit column stride)."""
+    if isinstance(a, torch.Tensor):
+        if a.is_cuda or a.dtype != torch.uint8 or a.dim() != 2 or (a.size(1) > 1 and a.stride(1) != 1):
+            raise ValueError("%s must be a 2-D uint8 CPU tensor with unit column stride" % name)
+        return a.size(0), a.size(1), a.stride(0), a.data_ptr()
+    a = np.asarray(a)
+    if a.dtype != np.uint8 or a.ndim != 2 or (a.shape[1] > 1 and a.strides[1] != 1):
+        raise ValueError("%s must be a 2-D uint8 array with unit column stride" % name)
+    return a.shape[0], a.shape[1], a.strides[0], a.ctypes.data
+
+
+class Pipe:
+    """Host-memory images -> host-memory magnitudes, with the copies to and
+    from the device overlapped with the kernels across `depth` slots."""
+
+    def __init__(self, max_width: int, max_height: int, depth: int = 3):
+        self._h = ctypes.c_void_p()
+        _check(lib.sobel4x5_pipe_create(max_width, max_height, depth, ctypes.byref(self._h)), "sobel4x5_pipe_create")
+
+    def run(self, srcs, mags=None, border: int = BORDER_REPLICATE):
+        """srcs: uint8 host images (numpy arrays or CPU tensors, pinned or
+        not); mags: matching outputs or None (numpy arrays are allocated)."""
+        n = len(srcs)
+        if mags is None:
+            mags = []
+            for m in srcs:
+                h, w = (m.shape[0], m.shape[1])
+                ho, wo = out_shape(h, w, border)
+                mags.append(np.empty((max(ho, 0), max(wo, 0)), np.uint8))
+        if len(mags) != n:
+            raise ValueError("srcs and mags differ in length")
+        arr = (Image * max(n, 1))()
+        for i, (sa, ma) in enumerate(zip(srcs, mags)):
+            h, w, sp, sptr = _host_rows(sa, "srcs[%d]" % i)
+            ho, wo = out_shape(h, w, border)
+            mh, mw, mp, mptr = _host_rows(ma, "mags[%d]" % i)
+            if (mh, mw) != (ho, wo):
+                raise ValueError("mags[%d] must have shape %s" % (i, (ho, wo)))
+            arr[i] = Image(sptr, mptr, w, h, sp, mp)
+        _check(lib.sobel4x5_pipe_run(self._h, arr, n, border), "sobel4x5_pipe_run")
+        return mags
+
+    def close(self):
+        if self._h:
+            lib.sobel4x5_pipe_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _images(srcs, mags, border):

@@ -528,6 +528,68 @@ std::string batch_key(const sobel4x5_image *imgs, int32_t count, int32_t border,
     return k;
 }
 
+
+// ------------------------------------------------------- host pipeline
+
+// One in-flight image of a pipeline: device buffers (sized for the largest
+// image), pinned staging buffers for callers whose host memory is pageable,
+// and a stream of its own (default priority).
+struct PipeSlot {
+    hipStream_t st = nullptr;
+    uint8_t *d_src = nullptr, *d_mag = nullptr;
+    uint8_t *h_src = nullptr, *h_mag = nullptr;   // pinned staging
+    int64_t pitch = 0;                            // device and staging row pitch
+    int pending = -1;                             // image whose magnitudes are in flight
+    bool staged_out = false;                      // D2H went to h_mag (copy on finish)
+};
+
+// true when p points to pinned (page-locked) host memory
+bool is_pinned(const void *p)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();   // pageable memory is not an error here
+        return false;
+    }
+    return a.type == hipMemoryTypeHost;
+}
+
+}  // namespace
+
+struct sobel4x5_pipe_s {
+    int32_t max_w = 0, max_h = 0;
+    std::vector<PipeSlot> slots;
+};
+
+namespace {
+
+void pipe_free(sobel4x5_pipe_s *p)
+{
+    for (auto &s : p->slots) {
+        if (s.st) hipStreamSynchronize(s.st);
+        if (s.d_src) hipFree(s.d_src);
+        if (s.d_mag) hipFree(s.d_mag);
+        if (s.h_src) hipHostFree(s.h_src);
+        if (s.h_mag) hipHostFree(s.h_mag);
+        if (s.st) hipStreamDestroy(s.st);
+        s = PipeSlot{};
+    }
+}
+
+// Copy the magnitudes of the slot's finished image out of pinned staging.
+void pipe_finish(PipeSlot &s, const sobel4x5_image *imgs, int32_t border)
+{
+    if (s.pending < 0) return;
+    if (s.staged_out) {
+        const sobel4x5_image &m = imgs[s.pending];
+        int32_t Wo, Ho;
+        out_dims(m.width, m.height, border, &Wo, &Ho);
+        for (int32_t r = 0; r < Ho; ++r) std::memcpy(m.mag + r * m.mag_pitch, s.h_mag + r * s.pitch, (size_t)Wo);
+    }
+    s.pending = -1;
+    s.staged_out = false;
+}
+
 }  // namespace
 
 extern "C" {
@@ -835,6 +897,101 @@ int sobel4x5_debug_round_mag(const int32_t *S, uint8_t *out, int64_t n, void *st
     if (n < 0 || (n > 0 && (!S || !out))) return fail(SOBEL4X5_EINVAL, "bad arguments");
     hipError_t e = launch_round_mag(S, out, n, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_debug_round_mag launch");
+}
+
+int sobel4x5_pipe_create(int32_t max_width, int32_t max_height, int32_t depth, sobel4x5_pipe *out)
+{
+    if (!out) return fail(SOBEL4X5_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_width < 1 || max_height < 1) return fail(SOBEL4X5_EINVAL, "max sizes must be >= 1");
+    if (depth < 1 || depth > 16) return fail(SOBEL4X5_EINVAL, "depth must be in [1, 16], got %d", depth);
+    auto *p = new (std::nothrow) sobel4x5_pipe_s;
+    if (!p) return fail(SOBEL4X5_ENOMEM, "host allocation failed");
+    p->max_w = max_width;
+    p->max_h = max_height;
+    p->slots.resize(depth);
+    const int64_t pitch = (max_width + 255) / 256 * 256;
+    const size_t bytes = (size_t)pitch * (size_t)max_height;
+    for (auto &sl : p->slots) {
+        sl.pitch = pitch;
+        hipError_t e;
+        if ((e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipMalloc(&sl.d_src, bytes)) != hipSuccess || (e = hipMalloc(&sl.d_mag, bytes)) != hipSuccess ||
+            (e = hipHostMalloc(&sl.h_src, bytes, hipHostMallocDefault)) != hipSuccess ||
+            (e = hipHostMalloc(&sl.h_mag, bytes, hipHostMallocDefault)) != hipSuccess) {
+            pipe_free(p);
+            delete p;
+            return fail(SOBEL4X5_ENOMEM, "pipeline allocation failed: %s", hipGetErrorString(e));
+        }
+    }
+    *out = p;
+    return ok();
+}
+
+int sobel4x5_pipe_run(sobel4x5_pipe p, const sobel4x5_image *imgs, int32_t count, int32_t border)
+{
+    if (!p) return fail(SOBEL4X5_EINVAL, "pipe is NULL");
+    if (count < 0 || (count > 0 && !imgs)) return fail(SOBEL4X5_EINVAL, "bad image array");
+    if (border != SOBEL4X5_BORDER_REPLICATE && border != SOBEL4X5_BORDER_VALID)
+        return fail(SOBEL4X5_EINVAL, "border must be 0 or 1, got %d", border);
+    for (int32_t i = 0; i < count; ++i) {
+        const sobel4x5_image &m = imgs[i];
+        int32_t Wo, Ho;
+        if (int rc = out_dims(m.width, m.height, border, &Wo, &Ho)) return rc;
+        if (!m.src || !m.mag) return fail(SOBEL4X5_EINVAL, "image %d: NULL pointer", i);
+        if (m.width > p->max_w || m.height > p->max_h)
+            return fail(SOBEL4X5_EINVAL, "image %d (%d x %d) exceeds the pipeline's %d x %d", i, m.width, m.height,
+                        p->max_w, p->max_h);
+        if (int rc = check_pitch("src", m.src_pitch, m.width, m.height)) return rc;
+        if (int rc = check_pitch("mag", m.mag_pitch, Wo, Ho)) return rc;
+    }
+    const int depth = (int)p->slots.size();
+    const bool valid = border == SOBEL4X5_BORDER_VALID;
+    auto drain = [&](PipeSlot &sl) -> hipError_t {
+        if (sl.pending < 0) return hipSuccess;
+        hipError_t e = hipStreamSynchronize(sl.st);
+        if (e == hipSuccess) pipe_finish(sl, imgs, border);
+        return e;
+    };
+    for (int32_t i = 0; i < count; ++i) {
+        PipeSlot &sl = p->slots[i % depth];
+        if (hipError_t e = drain(sl); e != hipSuccess) return hip_fail(e, "pipeline wait");
+        const sobel4x5_image &m = imgs[i];
+        int32_t Wo, Ho;
+        out_dims(m.width, m.height, border, &Wo, &Ho);
+        // host to device (pageable sources go through the slot's pinned
+        // staging buffer, so that the copy itself is asynchronous)
+        const uint8_t *hs = m.src;
+        int64_t hp = m.src_pitch;
+        if (!is_pinned(m.src)) {
+            for (int32_t r = 0; r < m.height; ++r)
+                std::memcpy(sl.h_src + r * sl.pitch, m.src + r * m.src_pitch, (size_t)m.width);
+            hs = sl.h_src;
+            hp = sl.pitch;
+        }
+        hipError_t e = hipMemcpy2DAsync(sl.d_src, sl.pitch, hs, hp, m.width, m.height, hipMemcpyHostToDevice, sl.st);
+        if (e != hipSuccess) return hip_fail(e, "pipeline host-to-device copy");
+        U8Job j = make_job(sl.d_src, m.width, m.height, sl.pitch, Wo, Ho, sl.d_mag, sl.pitch, nullptr, 0, 0);
+        const U8Shape shape = default_shape(Wo, Ho, SOBEL4X5_DIR_NONE);
+        u8_tile(j, shape);
+        if ((e = launch_u8_single(j, valid, shape, sl.st)) != hipSuccess) return hip_fail(e, "pipeline launch");
+        sl.staged_out = !is_pinned(m.mag);
+        e = hipMemcpy2DAsync(sl.staged_out ? sl.h_mag : m.mag, sl.staged_out ? sl.pitch : m.mag_pitch, sl.d_mag,
+                             sl.pitch, Wo, Ho, hipMemcpyDeviceToHost, sl.st);
+        if (e != hipSuccess) return hip_fail(e, "pipeline device-to-host copy");
+        sl.pending = i;
+    }
+    for (auto &sl : p->slots)
+        if (hipError_t e = drain(sl); e != hipSuccess) return hip_fail(e, "pipeline wait");
+    return ok();
+}
+
+int sobel4x5_pipe_destroy(sobel4x5_pipe p)
+{
+    if (!p) return fail(SOBEL4X5_EINVAL, "pipe is NULL");
+    pipe_free(p);
+    delete p;
+    return ok();
 }
 
 }  // extern "C"
