@@ -255,7 +255,7 @@ def bench_copy(torch, api, dev, steps):
 # and WRITE_SIZE (KiB per dispatch), scaled by what the same counters read for
 # the plain copy kernel (sobel4x5_debug_copy) of known size.  Valid only for
 # the kernel source they were taken on (its SHA-256 prefix); None otherwise.
-U8_TRAFFIC = {"src_sha256": "de34c41c5c79f387", "bytes": 144547889}   # profiles/k_u8_single_8192x8192_mag_u8.md
+U8_TRAFFIC = {"src_sha256": "95cc097372a3ce6f", "bytes": 144529085}   # profiles/k_u8_single_8192x8192_mag_u8.md
 
 
 def u8_traffic():

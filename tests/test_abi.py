@@ -122,3 +122,15 @@ def test_debug_round_mag_rejects_bad_args(sobel_lib):
     api = sobel_lib
     assert api.lib.sobel4x5_debug_round_mag(None, None, 5, None) == api.EINVAL
     assert api.lib.sobel4x5_debug_round_mag(None, None, -1, None) == api.EINVAL
+
+
+def test_pipe_arguments_are_checked_before_any_gpu_work(sobel_lib):
+    import ctypes
+    lib = sobel_lib.lib
+    h = ctypes.c_void_p()
+    assert lib.sobel4x5_pipe_create(64, 64, 0, ctypes.byref(h)) == sobel_lib.EINVAL     # depth 0
+    assert lib.sobel4x5_pipe_create(64, 64, 17, ctypes.byref(h)) == sobel_lib.EINVAL    # depth > 16
+    assert lib.sobel4x5_pipe_create(0, 64, 2, ctypes.byref(h)) == sobel_lib.EINVAL
+    assert lib.sobel4x5_pipe_create(64, 64, 2, None) == sobel_lib.EINVAL
+    assert lib.sobel4x5_pipe_run(None, None, 0, 0) == sobel_lib.EINVAL
+    assert lib.sobel4x5_pipe_destroy(None) == sobel_lib.EINVAL
