@@ -61,6 +61,8 @@ def _load():
         lib.oracle_f64_fwd_scale.restype = I
         lib.oracle_weights.argtypes = [P]
         lib.oracle_weights.restype = None
+        lib.oracle_u8_2dir.argtypes = [P, I, I, L, I, I, P, L, P, I]
+        lib.oracle_u8_2dir.restype = I
         lib.oracle_round_sqrt.argtypes = [ctypes.c_int64]
         lib.oracle_round_sqrt.restype = ctypes.c_int64
         _lib = lib
@@ -112,6 +114,27 @@ def sobel_u8(img: np.ndarray, border: int = REPLICATE, *, weights=None,
                            _ptr(wt), int(nthreads))
     if rc != 0:
         raise ValueError("oracle_u8 rejected its arguments (rc=%d)" % rc)
+    return mag, d
+
+
+def sobel_u8_2dir(img: np.ndarray, size: int, border: int = REPLICATE, *,
+                  want_mag: bool = True, want_dir: bool = True, nthreads: int = 0):
+    """Two-directional operator: (mag uint8 (Ho, Wo), dir int32 (2, Ho, Wo): Gx, Gy).
+
+    size 3: Eq. (sobel3_1) with Eq. (sobel3_2); VALID shrinks by 2.
+    size 5: the 0 and 90 deg filters of Eq. (sobel5_1); VALID shrinks by 4.
+    """
+    if img.dtype != np.uint8 or img.ndim != 2 or img.strides[1] != 1:
+        raise ValueError("img must be a 2-D uint8 array with unit column stride")
+    h, w = img.shape
+    r = size // 2
+    ho, wo = (h, w) if border == REPLICATE else (h - 2 * r, w - 2 * r)
+    mag = np.empty((max(ho, 0), max(wo, 0)), np.uint8) if want_mag else None
+    d = np.empty((2, max(ho, 0), max(wo, 0)), np.int32) if want_dir else None
+    rc = _load().oracle_u8_2dir(img.ctypes.data_as(ctypes.c_void_p), w, h, img.strides[0], border,
+                                int(size), _ptr(mag), max(wo, 1), _ptr(d), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_u8_2dir rejected its arguments (rc=%d)" % rc)
     return mag, d
 
 

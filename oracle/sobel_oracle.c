@@ -11,7 +11,10 @@
  * GPUs", Sec. 3.1):
  *   - four fixed 5x5 integer filters, Eq. (sobel5_1): 0 deg (Gx), 45 deg (Gd),
  *     90 deg (Gy), 135 deg (Gdt), each applied to every pixel;
- *   - the root-sum-of-squares magnitude, Eq. (sobel5_2).
+ *   - the root-sum-of-squares magnitude, Eq. (sobel5_2);
+ *   - the two-directional operators the paper compares against: the 3x3
+ *     Sobel pair of Eq. (sobel3_1) with Eq. (sobel3_2), and the 0 / 90 deg
+ *     pair of Eq. (sobel5_1) alone (oracle_u8_2dir).
  *
  * Readings where the paper is silent (each is listed in the design notes):
  *   - the filters are applied as a correlation: tap (i, j) of the printed
@@ -397,6 +400,83 @@ int oracle_f64_fwd_scale(const double *x, int B, int H, int W, int border, doubl
                         best = acc;
                 }
                 scale[b * plane_out + y * Wo + xo] = best;
+            }
+        }
+    }
+    return OR_OK;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Two-directional operators: the paper's comparison point.                */
+/* ---------------------------------------------------------------------- */
+
+/* Eq. (sobel3_1), typed in from the printed matrices: 0 deg (Gx), 90 deg
+ * (Gy).  Applied, like the 5x5 filters, as a correlation: tap (i, j)
+ * multiplies the pixel at row offset i-1, column offset j-1. */
+static const int32_t K3_PAPER[2][3][3] = {
+    {{-1, 0, 1},
+     {-2, 0, 2},
+     {-1, 0, 1}},
+    {{-1, -2, -1},
+     {0, 0, 0},
+     {1, 2, 1}},
+};
+
+/*
+ * Two-directional operator on a uint8 image: G = sqrt(Gx^2 + Gy^2),
+ * Eq. (sobel3_2).
+ *   size 3 : Gx, Gy of Eq. (sobel3_1); radius 1, so VALID shrinks the image
+ *            by 2: out(y, x) = full(y + 1, x + 1), W, H >= 3;
+ *   size 5 : Gx, Gy of Eq. (sobel5_1) (the 0 and 90 deg filters of the
+ *            four-directional operator); radius 2, VALID as for oracle_u8.
+ *   REPLICATE clamps every tap's row and column to the image (output H x W).
+ *   mag : Ho rows of Wo bytes at mag + r*mag_pitch, min(255, round(sqrt(S)))
+ *         (may be NULL);
+ *   dir : two int32 planes of Ho*Wo (Gx, then Gy), row-major (may be NULL).
+ */
+int oracle_u8_2dir(const uint8_t *src, int W, int H, long pitch, int border, int size,
+                   uint8_t *mag, long mag_pitch, int32_t *dir, int nthreads)
+{
+    if (!src || W <= 0 || H <= 0 || pitch < W || (size != 3 && size != 5))
+        return OR_EINVAL;
+    const int r = size / 2;
+    int Wo = W, Ho = H;
+    if (border == OR_BORDER_VALID) {
+        if (W < size || H < size)
+            return OR_EINVAL;
+        Wo = W - 2 * r;
+        Ho = H - 2 * r;
+    } else if (border != OR_BORDER_REPLICATE) {
+        return OR_EINVAL;
+    }
+    if (mag && mag_pitch < Wo)
+        return OR_EINVAL;
+    const long plane = (long)Wo * Ho;
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : omp_default_threads())
+    for (long y = 0; y < Ho; ++y) {
+        for (long x = 0; x < Wo; ++x) {
+            const long yc = border == OR_BORDER_VALID ? y + r : y;
+            const long xc = border == OR_BORDER_VALID ? x + r : x;
+            int64_t G[2];
+            for (int k = 0; k < 2; ++k) {
+                int64_t acc = 0;
+                for (int i = 0; i < size; ++i) {
+                    const long yy = clampl(yc + i - r, 0, H - 1);
+                    for (int j = 0; j < size; ++j) {
+                        const long xx = clampl(xc + j - r, 0, W - 1);
+                        const int32_t w = size == 3 ? K3_PAPER[k][i][j] : K_PAPER[2 * k][i][j];
+                        acc += (int64_t)w * (int64_t)src[yy * pitch + xx];
+                    }
+                }
+                G[k] = acc;
+            }
+            if (dir) {
+                dir[y * Wo + x] = (int32_t)G[0];
+                dir[plane + y * Wo + x] = (int32_t)G[1];
+            }
+            if (mag) {
+                const int64_t rr = round_sqrt_i64(G[0] * G[0] + G[1] * G[1]);
+                mag[y * mag_pitch + x] = (uint8_t)(rr > 255 ? 255 : rr);
             }
         }
     }
