@@ -7,7 +7,7 @@ Infinity Cache cannot serve them.  Secondary results (mixed-size batch in one
 persistent launch vs per-image launches, fp32 forward+backward, the size /
 output-type sweep) are reported in extra keys of the same JSON line.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--only u8|batched|f32|sweep]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--only u8,copy,sweep,ops,batched,f32,weighted,pipe]
                 [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -44,12 +44,12 @@ def parse():
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--only", default=None,
-                   help="comma-separated subset of: u8, copy, sweep, batched, f32, weighted, pipe")
+                   help="comma-separated subset of: u8, copy, sweep, ops, batched, f32, weighted, pipe")
     p.add_argument("--no-cpu-baseline", action="store_true")
     a = p.parse_args()
     if a.only is not None:
         a.only = set(x.strip() for x in a.only.split(",") if x.strip())
-        bad = a.only - {"u8", "copy", "sweep", "batched", "f32", "weighted", "pipe"}
+        bad = a.only - {"u8", "copy", "sweep", "ops", "batched", "f32", "weighted", "pipe"}
         if bad:
             p.error("unknown --only part(s): %s" % ", ".join(sorted(bad)))
     return a
@@ -130,6 +130,38 @@ def bench_sweep(torch, api, synth, dev, steps, warmup):
                                         "bytes_per_px": per // px}
             del srcs, outs, base
             torch.cuda.empty_cache()
+    return out
+
+
+def bench_ops(torch, api, synth, dev, steps, warmup):
+    """The paper's operator comparison (Sec. 5, Table 1: its four-directional
+    5x5 kernel against the 3x3 operator) on this GPU: the four-directional
+    5x5 operator, its 0 / 90 deg pair alone, and the two-directional 3x3
+    Sobel pair, uint8 magnitude only, replicate border, at Table 1's sizes
+    and at 8192^2."""
+    names = {api.OP_4DIR_5X5: "4dir_5x5", api.OP_2DIR_5X5: "2dir_5x5", api.OP_2DIR_3X3: "2dir_3x3"}
+    out = {}
+    for n in (512, 1024, 2048, 8192):
+        img = synth.rect_image(n, n, 3)
+        px = n * n
+        nsets = max(2, ROTATE_BYTES // (2 * px))
+        base = torch.from_numpy(img).to(dev)
+        srcs = [base.clone() for _ in range(nsets)]
+        mags = [torch.empty((n, n), dtype=torch.uint8, device=dev) for _ in range(nsets)]
+        row = {}
+        for op, name in names.items():
+            fn = lambda i, op=op: api.sobel4x5_u8_op(srcs[i % nsets], op, mag=mags[i % nsets])
+            k = max(20, steps * (4 if n <= 2048 else 1))
+            ms = time_launches(torch, fn, k, max(5, warmup))
+            gbs = 2 * px / (ms * 1e-3) / 1e9
+            row[name] = {"us": round(ms * 1e3, 3), "gpx_per_s": round(px / (ms * 1e-3) / 1e9, 2),
+                         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        row["time_ratio_4dir5x5_over_2dir3x3"] = round(row["4dir_5x5"]["us"] / row["2dir_3x3"]["us"], 3)
+        out["%d" % n] = row
+        del srcs, mags, base
+        torch.cuda.empty_cache()
+    out["note"] = ("back-to-back launches timed with HIP events over rotating buffers (>= 1 GiB); "
+                   "below 2048^2 a launch lasts a few microseconds, so launch gaps weigh in")
     return out
 
 
@@ -258,14 +290,24 @@ def bench_copy(torch, api, dev, steps):
 U8_TRAFFIC = {"src_sha256": "95cc097372a3ce6f", "bytes": 144529085}   # profiles/k_u8_single_8192x8192_mag_u8.md
 
 
-def u8_traffic():
+# Sources that define k_u8_single (the hash covers them in this order).
+U8_KERNEL_SOURCES = ("u8_sweep.hpp", "sobel4x5_u8.hip", "load_columns.hpp", "internal.hpp")
+
+
+def u8_source_hash():
     import hashlib
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2305_00515_amd", "csrc", "sobel4x5_u8.hip")
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2305_00515_amd", "csrc")
+    h = hashlib.sha256()
     try:
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        for name in U8_KERNEL_SOURCES:
+            h.update(open(os.path.join(csrc, name), "rb").read())
     except OSError:
         return None
-    return U8_TRAFFIC["bytes"] if h == U8_TRAFFIC["src_sha256"] else None
+    return h.hexdigest()[:16]
+
+
+def u8_traffic():
+    return U8_TRAFFIC["bytes"] if u8_source_hash() == U8_TRAFFIC["src_sha256"] else None
 
 
 def cpu_baseline(img):
@@ -342,6 +384,9 @@ def main():
     if want("sweep"):
         log("sweep")
         line["sweep"] = bench_sweep(torch, api, synth, dev, args.steps, args.warmup)
+    if want("ops"):
+        log("operator comparison (4-dir 5x5, 2-dir 5x5, 2-dir 3x3)")
+        line["ops"] = bench_ops(torch, api, synth, dev, args.steps, args.warmup)
     if want("batched"):
         log("batched 256 images")
         line["batched"] = bench_batched(torch, api, synth, dev, args.steps, args.warmup)

@@ -98,6 +98,40 @@ int sobel4x5_validate_u8(const uint8_t *src, int32_t width, int32_t height, int6
                          int32_t border, const sobel4x5_outputs *out);
 
 /*
+ * Operators.  Besides its four-directional 5x5 operator the paper defines
+ * the classic two-directional 3x3 Sobel pair, Eq. (sobel3_1) with the
+ * magnitude of Eq. (sobel3_2), and measures its kernels against the 3x3
+ * operator (Sec. 5, Table 1).
+ *   SOBEL4X5_OP_4DIR_5X5 : Eq. (sobel5_1) + Eq. (sobel5_2) (= sobel4x5_u8).
+ *   SOBEL4X5_OP_2DIR_5X5 : the 0 and 90 deg filters of Eq. (sobel5_1) alone,
+ *                          S = Gx^2 + Gy^2.
+ *   SOBEL4X5_OP_2DIR_3X3 : Eq. (sobel3_1) + Eq. (sobel3_2), tap (i, j)
+ *                          multiplying the pixel at offset (i-1, j-1); its
+ *                          radius is 1, so VALID shrinks the image by 2:
+ *                          output (H-2) x (W-2), out(y, x) =
+ *                          replicate(y+1, x+1), H, W >= 3.
+ */
+#define SOBEL4X5_OP_4DIR_5X5 0
+#define SOBEL4X5_OP_2DIR_5X5 1
+#define SOBEL4X5_OP_2DIR_3X3 2
+
+/*
+ * sobel4x5_u8_op -- sobel4x5_u8 for the operator `op` (SOBEL4X5_OP_*).
+ *   The two-directional operators write directional planes dir[0] (Gx,
+ *   0 deg) and dir[2] (Gy, 90 deg) only; dir[1] and dir[3] are ignored and
+ *   may be NULL.  Their int16 planes are exact (|G| <= 1020 for 3x3,
+ *   12240 for 5x5).  Magnitude min(255, round(sqrt(S))), exact.  Other
+ *   arguments, errors and layouts as for sobel4x5_u8; op 0 is sobel4x5_u8.
+ *   An unknown op is SOBEL4X5_EINVAL.
+ */
+int sobel4x5_u8_op(const uint8_t *src, int32_t width, int32_t height, int64_t src_pitch, int32_t op,
+                   int32_t border, const sobel4x5_outputs *out, void *stream);
+
+/* Host-only argument check of sobel4x5_u8_op (never touches the GPU). */
+int sobel4x5_validate_u8_op(const uint8_t *src, int32_t width, int32_t height, int64_t src_pitch,
+                            int32_t op, int32_t border, const sobel4x5_outputs *out);
+
+/*
  * Generalised weights (Sec. 3.2, Eq. (sobel5_param)).
  *
  * sobel4x5_u8_weighted -- sobel4x5_u8 with run-time integer kernels.

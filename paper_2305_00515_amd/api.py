@@ -25,6 +25,9 @@ BORDER_VALID = 1
 DIR_NONE = 0
 DIR_S16 = 1
 DIR_S32 = 2
+OP_4DIR_5X5 = 0     # Eq. (sobel5_1) + Eq. (sobel5_2)
+OP_2DIR_5X5 = 1     # the 0 and 90 deg filters of Eq. (sobel5_1)
+OP_2DIR_3X3 = 2     # Eq. (sobel3_1) + Eq. (sobel3_2)
 PLAN_AUTOTUNE = 1
 PLAN_NO_GRAPH = 2
 
@@ -58,6 +61,8 @@ def _load() -> ctypes.CDLL:
     sig = {
         "sobel4x5_u8": [P, I32, I32, I64, I32, ctypes.POINTER(Outputs), P],
         "sobel4x5_validate_u8": [P, I32, I32, I64, I32, ctypes.POINTER(Outputs)],
+        "sobel4x5_u8_op": [P, I32, I32, I64, I32, I32, ctypes.POINTER(Outputs), P],
+        "sobel4x5_validate_u8_op": [P, I32, I32, I64, I32, I32, ctypes.POINTER(Outputs)],
         "sobel4x5_plan_create": [ctypes.POINTER(Image), I32, I32, U32, ctypes.POINTER(P)],
         "sobel4x5_plan_launch": [P, P],
         "sobel4x5_plan_info": [P] + [ctypes.POINTER(I32)] * 4,
@@ -114,15 +119,18 @@ def _rows(t: torch.Tensor, name: str):
     return t.size(0), t.size(1), t.stride(0) * t.element_size()
 
 
-def out_shape(h: int, w: int, border: int):
-    return (h, w) if border == BORDER_REPLICATE else (h - 4, w - 4)
+def out_shape(h: int, w: int, border: int, op: int = OP_4DIR_5X5):
+    r = 1 if op == OP_2DIR_3X3 else 2
+    return (h, w) if border == BORDER_REPLICATE else (h - 2 * r, w - 2 * r)
 
 
-def _u8_outputs(src, border, mag, want_mag, dir_type, dirs):
-    """Outputs struct (and the tensors) for a uint8 call on src."""
+def _u8_outputs(src, border, mag, want_mag, dir_type, dirs, op=OP_4DIR_5X5):
+    """Outputs struct (and the tensors) for a uint8 call on src.  The
+    two-directional operators take two planes (Gx, Gy) in slots 0 and 2."""
     _need_cuda(src, torch.uint8, "src")
     h, w, pitch = _rows(src, "src")
-    ho, wo = out_shape(h, w, border)
+    ho, wo = out_shape(h, w, border, op)
+    slots = (0, 1, 2, 3) if op == OP_4DIR_5X5 else (0, 2)
     if want_mag and mag is None:
         mag = torch.empty((max(ho, 0), max(wo, 0)), dtype=torch.uint8, device=src.device)
     out = Outputs()
@@ -135,18 +143,18 @@ def _u8_outputs(src, border, mag, want_mag, dir_type, dirs):
     if dir_type != DIR_NONE:
         dt = torch.int16 if dir_type == DIR_S16 else torch.int32
         if dirs is None:
-            dirs = [torch.empty((ho, wo), dtype=dt, device=src.device) for _ in range(4)]
+            dirs = [torch.empty((ho, wo), dtype=dt, device=src.device) for _ in slots]
         pitches = set()
-        if len(dirs) != 4:
-            raise ValueError("need four directional planes")
-        for k, d in enumerate(dirs):
+        if len(dirs) != len(slots):
+            raise ValueError("need %d directional planes" % len(slots))
+        for k, d in zip(slots, dirs):
             _need_cuda(d, dt, "dirs[%d]" % k)
             if tuple(d.shape) != (ho, wo):
                 raise ValueError("dirs[%d] must have shape %s" % (k, (ho, wo)))
             out.dir[k] = d.data_ptr()
             pitches.add(_rows(d, "dirs[%d]" % k)[2])
         if len(pitches) != 1:
-            raise ValueError("all four directional planes must share one row pitch")
+            raise ValueError("all directional planes must share one row pitch")
         out.dir_pitch = pitches.pop()
     out.dir_type = dir_type
     res = ((mag if (want_mag or out.mag) else None), (dirs if dir_type != DIR_NONE else None))
@@ -163,6 +171,17 @@ def sobel4x5_u8(src: torch.Tensor, border: int = BORDER_REPLICATE, *, mag: torch
     out, (h, w, pitch), res = _u8_outputs(src, border, mag, want_mag, dir_type, dirs)
     _check(lib.sobel4x5_u8(src.data_ptr(), w, h, pitch, border, ctypes.byref(out), _stream(src)),
            "sobel4x5_u8")
+    return res
+
+
+def sobel4x5_u8_op(src: torch.Tensor, op: int, border: int = BORDER_REPLICATE, *,
+                   mag: torch.Tensor | None = None, want_mag: bool = True, dir_type: int = DIR_NONE,
+                   dirs: list | None = None):
+    """sobel4x5_u8 for operator `op` (OP_*): the two-directional operators
+    return two planes [Gx, Gy]; the 3x3 pair's VALID output is (H-2, W-2)."""
+    out, (h, w, pitch), res = _u8_outputs(src, border, mag, want_mag, dir_type, dirs, op)
+    _check(lib.sobel4x5_u8_op(src.data_ptr(), w, h, pitch, op, border, ctypes.byref(out), _stream(src)),
+           "sobel4x5_u8_op")
     return res
 
 

@@ -8,6 +8,8 @@ import os
 import shutil
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 from pathlib import Path
 
 PKG = Path(__file__).resolve().parent
@@ -16,7 +18,8 @@ CSRC = PKG / "csrc"
 LIB = PKG / "libsobel4x5.so"
 ARCH = os.environ.get("SOBEL4X5_ARCH", "gfx950")
 
-SOURCES = ["sobel4x5_api.cpp", "sobel4x5_u8.hip", "sobel4x5_f32.hip", "sobel4x5_weighted.hip"]
+SOURCES = ["sobel4x5_api.cpp", "sobel4x5_u8.hip", "sobel_2dir_u8.hip", "sobel4x5_f32.hip",
+           "sobel4x5_weighted.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -35,25 +38,46 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, out: Path | None = None, defines=()) -> Path:
-    """Compile every source into libsobel4x5.so (always recompiles).
-
-    ``out`` and ``defines`` (NAME=VALUE strings) build a variant elsewhere,
-    for tuning experiments; the package always loads LIB unless
-    SOBEL4X5_LIBRARY names another build.
-    """
-    out = Path(out) if out else LIB
-    tmp = out.with_suffix(".so.tmp%d" % os.getpid())
-    cmd = [hipcc()] + FLAGS + ["-D" + d for d in defines] + ["-o", str(tmp)] + [str(CSRC / s) for s in SOURCES]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libsobel4x5.so")
-    if verbose and res.stderr.strip():
+    elif verbose and res.stderr.strip():
         sys.stderr.write(res.stderr)
-    os.replace(tmp, out)
+    return res.returncode
+
+
+def build(verbose: bool = False, out: Path | None = None, defines=()) -> Path:
+    """Compile every source into libsobel4x5.so (always recompiles).
+
+    The translation units compile in parallel into a scratch folder, then
+    link.  ``out`` and ``defines`` (NAME=VALUE strings) build a variant
+    elsewhere, for tuning experiments; the package always loads LIB unless
+    SOBEL4X5_LIBRARY names another build.
+    """
+    out = Path(out) if out else LIB
+    objdir = Path(tempfile.mkdtemp(prefix="s4x5_obj_"))
+    try:
+        dflags = ["-D" + d for d in defines]
+        compile_flags = [f for f in FLAGS if f != "-shared"]
+        jobs = []
+        for src in SOURCES:
+            obj = objdir / (Path(src).stem + ".o")
+            jobs.append((obj, [hipcc()] + compile_flags + dflags + ["-c", "-o", str(obj), str(CSRC / src)]))
+        workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            codes = list(ex.map(lambda j: _run(j[1], verbose), jobs))
+        if any(codes):
+            raise RuntimeError("hipcc failed building libsobel4x5.so")
+        tmp = out.with_suffix(".so.tmp%d" % os.getpid())
+        link = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", str(tmp)] + [str(o) for o, _ in jobs]
+        if _run(link, verbose):
+            raise RuntimeError("linking libsobel4x5.so failed")
+        os.replace(tmp, out)
+    finally:
+        shutil.rmtree(objdir, ignore_errors=True)
     return out
 
 

@@ -11,7 +11,8 @@ namespace s4x5 {
 
 // One uint8 image as the kernels see it.  Output pixel (yo, xo) is the
 // operator centred on input pixel (yo + off, xo + off): off = 0 for the
-// replicate border, 2 for the valid border.
+// replicate border, the operator's radius (2, or 1 for the 3x3 pair) for the
+// valid border.
 struct U8Job {
     const uint8_t *src;
     uint8_t *mag;          // may be null
@@ -49,6 +50,12 @@ void u8_tile(U8Job &j, const U8Shape &s);
 // one strip of four tiles.
 hipError_t launch_u8_single(const U8Job &j, int border_valid, const U8Shape &s,
                             hipStream_t stream);
+
+// Two-directional operators on the single-image sweep: op 1 = the 0 / 90 deg
+// filters of the 5x5 operator, op 2 = the 3x3 pair (VALID: off = 1).  The
+// job's Wo, Ho and tiling are those of the operator's own border rule.
+hipError_t launch_u8_2dir(const U8Job &j, int op, int border_valid, const U8Shape &s,
+                          hipStream_t stream);
 
 // Batched persistent launch (`aligned`: every image has 16-byte aligned src
 // rows).  `jobs` (device) holds the images; `tiles` (device, `total`

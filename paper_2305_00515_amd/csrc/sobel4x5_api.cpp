@@ -46,22 +46,28 @@ int hip_fail(hipError_t e, const char *what)
 
 constexpr int64_t kMaxDim = 1 << 30;
 
-int out_dims(int32_t W, int32_t H, int32_t border, int32_t *Wo, int32_t *Ho)
+// Output size of an operator of radius r (2 for the 5x5 filters, 1 for 3x3).
+int out_dims_r(int32_t W, int32_t H, int32_t border, int r, int32_t *Wo, int32_t *Ho)
 {
     if (border != SOBEL4X5_BORDER_REPLICATE && border != SOBEL4X5_BORDER_VALID)
         return fail(SOBEL4X5_EINVAL, "border must be REPLICATE (0) or VALID (1), got %d", border);
     if (W < 1 || H < 1) return fail(SOBEL4X5_EINVAL, "width and height must be >= 1 (got %d x %d)", W, H);
     if (W > kMaxDim || H > kMaxDim) return fail(SOBEL4X5_EINVAL, "image too large");
     if (border == SOBEL4X5_BORDER_VALID) {
-        if (W < 5 || H < 5)
-            return fail(SOBEL4X5_EINVAL, "VALID border needs width and height >= 5 (got %d x %d)", W, H);
-        *Wo = W - 4;
-        *Ho = H - 4;
+        if (W < 2 * r + 1 || H < 2 * r + 1)
+            return fail(SOBEL4X5_EINVAL, "VALID border needs width and height >= %d (got %d x %d)", 2 * r + 1, W, H);
+        *Wo = W - 2 * r;
+        *Ho = H - 2 * r;
     } else {
         *Wo = W;
         *Ho = H;
     }
     return ok();
+}
+
+int out_dims(int32_t W, int32_t H, int32_t border, int32_t *Wo, int32_t *Ho)
+{
+    return out_dims_r(W, H, border, 2, Wo, Ho);
 }
 
 struct Range {
@@ -85,11 +91,15 @@ int check_pitch(const char *name, int64_t pitch, int64_t row_bytes, int64_t rows
     return ok();
 }
 
+// Arguments of one uint8 image for operator `op` (SOBEL4X5_OP_*): the
+// two-directional operators write directional planes 0 and 2 only.
 int validate_u8(const uint8_t *src, int32_t W, int32_t H, int64_t pitch, int32_t border,
-                const sobel4x5_outputs *out, int32_t *pWo, int32_t *pHo)
+                const sobel4x5_outputs *out, int32_t *pWo, int32_t *pHo, int32_t op = SOBEL4X5_OP_4DIR_5X5)
 {
     int32_t Wo, Ho;
-    if (int rc = out_dims(W, H, border, &Wo, &Ho)) return rc;
+    if (op != SOBEL4X5_OP_4DIR_5X5 && op != SOBEL4X5_OP_2DIR_5X5 && op != SOBEL4X5_OP_2DIR_3X3)
+        return fail(SOBEL4X5_EINVAL, "op must be 0, 1 or 2, got %d", op);
+    if (int rc = out_dims_r(W, H, border, op == SOBEL4X5_OP_2DIR_3X3 ? 1 : 2, &Wo, &Ho)) return rc;
     if (!src) return fail(SOBEL4X5_EINVAL, "src is NULL");
     if (!out) return fail(SOBEL4X5_EINVAL, "out is NULL");
     if (int rc = check_pitch("src", pitch, W, H)) return rc;
@@ -109,6 +119,7 @@ int validate_u8(const uint8_t *src, int32_t W, int32_t H, int64_t pitch, int32_t
         if (int rc = check_pitch("dir", out->dir_pitch, (int64_t)Wo * es, Ho)) return rc;
         if (out->dir_pitch % es) return fail(SOBEL4X5_EINVAL, "dir pitch must be a multiple of the element size");
         for (int k = 0; k < 4; ++k) {
+            if (op != SOBEL4X5_OP_4DIR_5X5 && (k & 1)) continue;
             if (!out->dir[k]) return fail(SOBEL4X5_EINVAL, "dir[%d] is NULL", k);
             if (reinterpret_cast<uintptr_t>(out->dir[k]) % es)
                 return fail(SOBEL4X5_EINVAL, "dir[%d] is not aligned to its element size", k);
@@ -628,6 +639,32 @@ int sobel4x5_u8(const uint8_t *src, int32_t width, int32_t height, int64_t src_p
     u8_tile(j, s);
     hipError_t e = launch_u8_single(j, border == SOBEL4X5_BORDER_VALID, s, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_u8 launch");
+}
+
+int sobel4x5_validate_u8_op(const uint8_t *src, int32_t width, int32_t height, int64_t src_pitch, int32_t op,
+                            int32_t border, const sobel4x5_outputs *out)
+{
+    int32_t Wo, Ho;
+    return validate_u8(src, width, height, src_pitch, border, out, &Wo, &Ho, op);
+}
+
+int sobel4x5_u8_op(const uint8_t *src, int32_t width, int32_t height, int64_t src_pitch, int32_t op,
+                   int32_t border, const sobel4x5_outputs *out, void *stream)
+{
+    int32_t Wo, Ho;
+    if (int rc = validate_u8(src, width, height, src_pitch, border, out, &Wo, &Ho, op)) return rc;
+    if (op == SOBEL4X5_OP_4DIR_5X5) return sobel4x5_u8(src, width, height, src_pitch, border, out, stream);
+    void *dirs[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (out->dir_type) {
+        dirs[0] = out->dir[0];
+        dirs[2] = out->dir[2];
+    }
+    U8Job j = make_job(src, width, height, src_pitch, Wo, Ho, out->mag, out->mag_pitch,
+                       out->dir_type ? dirs : nullptr, out->dir_pitch, out->dir_type);
+    const U8Shape s = default_shape(Wo, Ho, out->dir_type);
+    u8_tile(j, s);
+    hipError_t e = launch_u8_2dir(j, op, border == SOBEL4X5_BORDER_VALID, s, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_u8_op launch");
 }
 
 int sobel4x5_validate_batch(const sobel4x5_image *imgs, int32_t count, int32_t border)

@@ -1,0 +1,713 @@
+// uint8 Sobel sweep for CDNA4 (gfx950), shared by the kernels of the
+// four-directional 5x5 operator and of the two-directional operators.
+//
+// Operator: Eq. (sobel5_1) and Eq. (sobel5_2) of Chang et al. (Sec. 3.1),
+// applied as a correlation.  The four responses are never formed tap by tap.
+// They come from shared one-dimensional passes, in the spirit of the paper's
+// separable row filters (Sec. 4.3, Eq. (Fx)/(Gx)) and its diagonal transform
+// (K_d+- = K_d +- K_dt, Eq. (sobel5_kd+-); K_d- as a sum of two separable
+// terms, Eq. (sobel5_4)):
+//
+//   Gx  = c_v(h_r)                     rows first:  h_r = [-1,-2,0,2,1] . row
+//   Gd- = c'_v(h_r) - d_v(h_s)                       h_s = [0,-1,0,1,0] . row
+//   Gy  = c_h(v_r)                     columns first: v_r = [-1,-2,0,2,1]^T . col
+//   Gd+ = c'_h(v_r) - d_h(v_s)                         v_s = [0,-1,0,1,0]^T . col
+//
+// with c = [1,4,6,4,1], c' = [6,6,2,6,6], d = [10,0,-12,0,10].  K_d+ is the
+// transpose of K_d-, so the transpose of Eq. (sobel5_4) gives the Gd+ line.
+// Then Gd = (Gd+ + Gd-)/2 and Gdt = (Gd+ - Gd-)/2 (Eq. (sobel5_kd), exact)
+// and 2S = 2(Gx^2 + Gy^2) + Gd+^2 + Gd-^2.
+//
+// Every intermediate fits in int16 (|G| <= 12240, |Gd+-| <= 17850, partial
+// sums <= 28050), so the passes run on packed 16-bit lanes: one register
+// holds pixels j and j + ppl/2 of a lane's ppl consecutive pixels.  The
+// squares are summed with v_dot2_i32_i16 after a byte permute that pairs
+// (Gx, Gy) and (Gd+, Gd-) of the same pixel.
+//
+// Memory side (replaces the paper's warp shuffles and one-row prefetch):
+//   - a lane loads its ppl pixels of a row with one 128-/64-bit load;
+//   - the two halo bytes on each side come from the neighbouring lanes by
+//     DPP row_shr/row_shl inside a 16-lane row; the 16-lane group's outer
+//     halo comes from one extra dword load by its first and last lane;
+//   - a group sweeps its tile top to bottom, keeping a 5-row ring of the
+//     unpacked rows and of the row filters in VGPRs (the ring index is the
+//     loop phase, unrolled by 5), and loads PD rows ahead;
+//   - the right image border (and widths that are not a multiple of 16) is
+//     handled in registers: the lane's aligned 16-byte block is always a
+//     block that holds a valid byte of the row, and bytes past the row end
+//     are replaced by the last valid pixel (replicate).
+//
+// The same sweep serves the two-directional operators the paper compares
+// with (Sec. 3.1, Sec. 5): the 0 and 90 deg filters of Eq. (sobel5_1) alone,
+// and the 3x3 pair of Eq. (sobel3_1), whose filters are [1, 2, 1]
+// smoothings of the central differences h_s and v_s the 5x5 passes already
+// form.  Their magnitude is Eq. (sobel3_2), S = Gx^2 + Gy^2.
+
+#pragma once
+
+#include "internal.hpp"
+#include "load_columns.hpp"
+
+#include <algorithm>
+#include <mutex>
+#include <type_traits>
+#include <utility>
+#include <vector>
+
+namespace s4x5 {
+namespace {
+
+typedef short v2s __attribute__((ext_vector_type(2)));
+
+// Image and output accesses go through global-address-space pointers.  A
+// pointer read from memory (the batched job table) is otherwise a generic
+// pointer, accessed with FLAT instructions, which count in both vmcnt and
+// lgkmcnt and may complete out of order: every wait for one becomes a full
+// drain of the row prefetch.
+#define GMEM __attribute__((address_space(1)))
+typedef unsigned int gv4u __attribute__((ext_vector_type(4)));
+typedef unsigned int gv2u __attribute__((ext_vector_type(2)));
+// Output rows need no alignment: the HSA runtime runs the GPU in unaligned
+// access mode, so a 16-byte store at any byte address is one
+// global_store_dwordx4 that writes exactly those 16 bytes.
+typedef gv4u gv4u_u __attribute__((aligned(1)));
+typedef gv2u gv2u_u __attribute__((aligned(1)));
+typedef unsigned int u32;
+
+__device__ __forceinline__ v2s S2(u32 v) { return __builtin_bit_cast(v2s, v); }
+__device__ __forceinline__ u32 U2(v2s v) { return __builtin_bit_cast(u32, v); }
+__device__ __forceinline__ u32 perm(u32 hi, u32 lo, u32 sel) { return __builtin_amdgcn_perm(hi, lo, sel); }
+
+constexpr u32 kZeroByte = 0x0c;   // v_perm selector that yields 0x00
+constexpr int kPD = 4;            // rows loaded ahead of use
+
+// Operators the sweep computes (the values of the public SOBEL4X5_OP_*).
+constexpr int kOp4x5 = 0;   // Eq. (sobel5_1) + Eq. (sobel5_2): four directions, 5x5
+constexpr int kOp2x5 = 1;   // the 0 and 90 deg filters of Eq. (sobel5_1) alone
+constexpr int kOp2x3 = 2;   // Eq. (sobel3_1) + Eq. (sobel3_2): the 3x3 pair
+
+// v_perm selector: byte0 <- byte `lob` of the low source, byte2 <- byte
+// `hib` of the high source, bytes 1 and 3 <- 0: two zero-extended pixels.
+constexpr u32 pair_sel(int lob, int hib)
+{
+    return (kZeroByte << 24) | ((4u + (u32)hib) << 16) | (kZeroByte << 8) | (u32)lob;
+}
+
+// Round-to-nearest of sqrt(S), saturated to 255.  (float)S is exact below
+// 2^24 and monotone above, where the result saturates anyway; v_sqrt_f32 is
+// within 1 ulp, and an integer S is never closer than 4.9e-4 to a
+// half-integer square root, so rounding the float result is exact.
+__device__ __forceinline__ float mag_f(int S) { return __builtin_amdgcn_sqrtf((float)S); }
+
+__device__ __forceinline__ u32 round_mag(int S)
+{
+    // v_cvt_pk_u8_f32: round to nearest, saturate to [0, 255] (no ties occur)
+    return __builtin_amdgcn_cvt_pk_u8_f32(mag_f(S), 0, 0u);
+}
+
+// a.lo^2 + a.hi^2 of two int16 halves (VOP3P dot with a zero accumulator)
+__device__ __forceinline__ int dot2_sq(u32 a)
+{
+    int r;
+    asm("v_dot2_i32_i16 %0, %1, %1, 0" : "=v"(r) : "v"(a));
+    return r;
+}
+
+// A packed (c, c) constant the optimiser cannot see through, so that
+// products with it stay single v_pk_mad_u16 instructions instead of being
+// strength-reduced into shift + add pairs.
+template <int C>
+__device__ __forceinline__ v2s kconst()
+{
+    u32 r;
+    asm("s_mov_b32 %0, %1" : "=s"(r) : "i"((int)(((unsigned)C & 0xffffu) | ((unsigned)C << 16))));
+    return S2(r);
+}
+
+// The 20-byte window of one lane for one row: the lane's own ppl bytes
+// d[0..ppl/4) starting at column xo, L (bytes 2, 3 = columns xo-2, xo-1) and
+// Rt (bytes 0..3 = columns xo+ppl .. xo+ppl+3).
+template <int PPL>
+struct Win {
+    u32 L;
+    u32 d[PPL / 4];
+    u32 Rt;
+};
+
+// Window byte w covers column xo - 2 + w.
+template <int PPL>
+__device__ __forceinline__ u32 win_word(const Win<PPL> &w, int b)
+{
+    if (b < 2) return w.L;
+    if (b < PPL + 2) return w.d[(b - 2) >> 2];
+    return w.Rt;
+}
+template <int PPL>
+constexpr int win_byte(int b)
+{
+    return b < 2 ? b + 2 : (b < PPL + 2 ? ((b - 2) & 3) : b - PPL - 2);
+}
+
+// Unpack a window into NP + 4 packed registers R[j + 2] = (p[j], p[j + NP]),
+// j in [-2, NP + 2), where p[j] is the pixel at column (first centre + j) and
+// the first centre is column xo + OFF.
+template <int PPL, int OFF>
+__device__ __forceinline__ void unpack(const Win<PPL> &w, v2s (&R)[PPL / 2 + 4])
+{
+    constexpr int NP = PPL / 2;
+#pragma unroll
+    for (int j = -2; j < NP + 2; ++j) {
+        const int bl = OFF + j + 2, bh = OFF + j + NP + 2;
+        R[j + 2] = S2(perm(win_word<PPL>(w, bh), win_word<PPL>(w, bl),
+                           pair_sel(win_byte<PPL>(bl), win_byte<PPL>(bh))));
+    }
+}
+
+// Row filters of one input row (Eq. (Fx) and the D term of Eq. (Gd-_fast)):
+// h_s = p[+1] - p[-1], h_r = (p[+2] - p[-2]) + 2 h_s.
+template <int NP>
+__device__ __forceinline__ void row_filters(const v2s (&R)[NP + 4], v2s (&hr)[NP], v2s (&hs)[NP])
+{
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        v2s s = R[j + 3] - R[j + 1];
+        v2s e = R[j + 4] - R[j];
+        hs[j] = s;
+        hr[j] = s * kconst<2>() + e;
+    }
+}
+
+// Gy and Hp = Gd+/2 at one output row (columns first).  vr = v_r and a2 =
+// v_s of the output row's centre, both for NP + 4 columns.  Every entry of
+// K_d+ and K_d- is even, so Gd+/2 and Gd-/2 are integers and take one
+// multiply-add less than Gd+- itself.
+template <int NP>
+__device__ __forceinline__ void responses_y(const v2s (&vr)[NP + 4], const v2s (&a2)[NP + 4],
+                                            v2s (&Gy)[NP], v2s (&Hp)[NP])
+{
+    const v2s k3 = kconst<3>(), k4 = kconst<4>(), k6 = kconst<6>(), km5 = kconst<-5>();
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const int c = j + 2;
+        v2s p4 = vr[c - 2] + vr[c + 2];
+        v2s p2 = vr[c - 1] + vr[c + 1];
+        Gy[j] = vr[c] * k6 + (p2 * k4 + p4);
+        v2s t = (p4 + p2) * k3 + vr[c];
+        t = (a2[c - 2] + a2[c + 2]) * km5 + t;
+        Hp[j] = a2[c] * k6 + t;
+    }
+}
+
+// Gx and Hm = Gd-/2 at one output row (rows first) from the row filters of
+// the five window rows.
+template <int NP>
+__device__ __forceinline__ void responses_x(const v2s (&hr0)[NP], const v2s (&hr1)[NP],
+                                            const v2s (&hr2)[NP], const v2s (&hr3)[NP],
+                                            const v2s (&hr4)[NP], const v2s (&hs0)[NP],
+                                            const v2s (&hs2)[NP], const v2s (&hs4)[NP],
+                                            v2s (&Gx)[NP], v2s (&Hm)[NP])
+{
+    const v2s k3 = kconst<3>(), k4 = kconst<4>(), k6 = kconst<6>(), km5 = kconst<-5>();
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        v2s x1 = hr0[j] + hr4[j];
+        v2s x2 = hr1[j] + hr3[j];
+        Gx[j] = hr2[j] * k6 + (x2 * k4 + x1);
+        v2s t = (x1 + x2) * k3 + hr2[j];
+        t = (hs0[j] + hs4[j]) * km5 + t;
+        Hm[j] = hs2[j] * k6 + t;
+    }
+}
+
+// Gx and Gy of Eq. (sobel3_1) at one output row.  Both filters are a
+// [1, 2, 1] smoothing of a central difference: Gx smooths the row
+// differences h_s of the rows above, at and below the centre; Gy smooths
+// the column differences v_s (row below minus row above, a2 = v_s of the
+// centre row for NP + 4 columns) over the three columns around the centre.
+template <int NP>
+__device__ __forceinline__ void responses_3x3(const v2s (&hs0)[NP], const v2s (&hs1)[NP],
+                                              const v2s (&hs2)[NP], const v2s (&a2)[NP + 4],
+                                              v2s (&Gx)[NP], v2s (&Gy)[NP])
+{
+    const v2s k2 = kconst<2>();
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        Gx[j] = hs1[j] * k2 + (hs0[j] + hs2[j]);
+        Gy[j] = a2[j + 2] * k2 + (a2[j + 1] + a2[j + 3]);
+    }
+}
+
+// Replace the bytes of `v` at positions >= keep (0..4) by `fill` (a byte
+// replicated four times).
+__device__ __forceinline__ u32 keep_bytes(u32 v, int keep, u32 fill)
+{
+    u32 mask = keep >= 4 ? 0xffffffffu : ((1u << (8 * (keep > 0 ? keep : 0))) - 1u);
+    return (v & mask) | (fill & ~mask);
+}
+
+// Byte b (runtime, 0..PPL-1) of the lane's own block, by v_perm with a
+// runtime selector (keeps the block in registers).
+template <int PPL>
+__device__ __forceinline__ u32 byte_of(const u32 (&d)[PPL / 4], int b)
+{
+    u32 lo = d[0], hi = d[1];
+    if constexpr (PPL == 16) {
+        const bool up = (b & 8) != 0;
+        lo = up ? d[2] : d[0];
+        hi = up ? d[3] : d[1];
+    }
+    return perm(hi, lo, (kZeroByte << 24) | (kZeroByte << 16) | (kZeroByte << 8) | (u32)(b & 7));
+}
+
+template <int PPL>
+struct RawRow {
+    u32 d[PPL / 4];
+    u32 hw;   // lane 0 of a group: left halo dword; lane 15: right halo dword
+};
+
+// Issue the loads of one row (fast path: 16-byte aligned rows).
+template <int PPL>
+__device__ __forceinline__ void load_row(RawRow<PPL> &r, const GMEM uint8_t *rowp, unsigned ldx, unsigned hx)
+{
+    if constexpr (PPL == 16) {
+        const gv4u v = *reinterpret_cast<const GMEM gv4u *>(rowp + ldx);
+        r.d[0] = v.x; r.d[1] = v.y; r.d[2] = v.z; r.d[3] = v.w;
+    } else {
+        const gv2u v = *reinterpret_cast<const GMEM gv2u *>(rowp + ldx);
+        r.d[0] = v.x; r.d[1] = v.y;
+    }
+    r.hw = *reinterpret_cast<const GMEM u32 *>(rowp + hx);
+}
+
+// Turn a loaded row into the lane's window: border fix-ups, then DPP halo.
+template <int PPL, int OFF>
+__device__ __forceinline__ Win<PPL> finish_row(RawRow<PPL> &r, int lane16, int xo, int W,
+                                               bool fix_right, bool fix_left)
+{
+    constexpr int ND = PPL / 4;
+    if (fix_right) {
+        // own block: bytes at columns >= W take the value of column W-1
+        const int nv = W - xo;
+        if (nv < PPL) {
+            const int lb = nv >= 1 ? nv - 1 : ((W - 1) & (PPL - 1));
+            const u32 fill = byte_of<PPL>(r.d, lb) * 0x01010101u;
+#pragma unroll
+            for (int m = 0; m < ND; ++m) r.d[m] = keep_bytes(r.d[m], nv - 4 * m, fill);
+        }
+        // right halo dword of lane 15 (nominal columns xo+PPL .. xo+PPL+3)
+        const int nh = W - (xo + PPL);
+        if (lane16 == 15 && nh < 4) {
+            const int lb = nh >= 1 ? nh - 1 : ((W - 1) & 3);
+            const u32 fill = ((r.hw >> (8 * lb)) & 0xffu) * 0x01010101u;
+            r.hw = keep_bytes(r.hw, nh, fill);
+        }
+    }
+    if (OFF == 0 && fix_left && lane16 == 0 && xo == 0) r.hw = (r.d[0] & 0xffu) * 0x01010101u;
+    Win<PPL> w;
+#pragma unroll
+    for (int m = 0; m < ND; ++m) w.d[m] = r.d[m];
+    // row_shr:1 -> value of lane-1 within the 16-lane row; lane 0 keeps `old`
+    w.L = (u32)__builtin_amdgcn_update_dpp((int)r.hw, (int)r.d[ND - 1], 0x111, 0xf, 0xf, false);
+    // row_shl:1 -> value of lane+1; lane 15 keeps `old`
+    w.Rt = (u32)__builtin_amdgcn_update_dpp((int)r.hw, (int)r.d[0], 0x101, 0xf, 0xf, false);
+    return w;
+}
+
+// Replicate fix-ups of the group halo dwords for a fast wave at the image's
+// left / right edge (its lanes' own blocks all lie inside the row): loop-
+// invariant per-lane masks, so the fix-up is two v_perm + two v_bfi per row
+// and no branch.  mask bits set = keep the loaded byte.
+struct EdgeFix {
+    u32 keep_l;   // lane 0 at column 0 (replicate border): 0, else all ones
+    u32 keep_r;   // lane 15 whose halo reaches column W: bytes < W - (xo + ppl), else all ones
+    u32 sel_r;    // v_perm selector replicating the byte of column W-1 from (hw, last own dword)
+};
+
+template <int PPL, int OFF>
+__device__ __forceinline__ EdgeFix edge_fix(int lane16, int xo, int W, bool at_left, bool at_right)
+{
+    EdgeFix e;
+    e.keep_l = (OFF == 0 && at_left && lane16 == 0 && xo == 0) ? 0u : ~0u;
+    const int nh = W - (xo + PPL);   // valid bytes of the right halo dword (>= 0 here)
+    const bool r = at_right && lane16 == 15 && nh < 4;
+    e.keep_r = r ? ((1u << (8 * nh)) - 1u) : ~0u;
+    e.sel_r = (nh >= 1 ? (u32)(4 + nh - 1) : 3u) * 0x01010101u;
+    return e;
+}
+
+template <int PPL>
+__device__ __forceinline__ void apply_edge(RawRow<PPL> &r, const EdgeFix &e)
+{
+    constexpr int ND = PPL / 4;
+    const u32 fr = perm(r.hw, r.d[ND - 1], e.sel_r);   // column W-1, four times
+    const u32 fl = perm(r.d[0], r.d[0], 0u);            // column 0, four times
+    r.hw = (r.hw & e.keep_r) | (fr & ~e.keep_r);
+    r.hw = (r.hw & e.keep_l) | (fl & ~e.keep_l);
+}
+
+// Slow path for rows that are not 16-byte aligned: every window byte is read
+// on its own at its clamped column.
+template <int PPL>
+__device__ __forceinline__ Win<PPL> load_row_bytes(const GMEM uint8_t *rowp, int xo, int W)
+{
+    Win<PPL> w;
+    auto px = [&](int x) -> u32 { return rowp[x < 0 ? 0 : (x >= W ? W - 1 : x)]; };
+    w.L = (px(xo - 2) << 16) | (px(xo - 1) << 24);
+#pragma unroll
+    for (int m = 0; m < PPL / 4; ++m) {
+        const int x = xo + 4 * m;
+        w.d[m] = px(x) | (px(x + 1) << 8) | (px(x + 2) << 16) | (px(x + 3) << 24);
+    }
+    const int x = xo + PPL;
+    w.Rt = px(x) | (px(x + 1) << 8) | (px(x + 2) << 16) | (px(x + 3) << 24);
+    return w;
+}
+
+// Stores of one output row for one lane, from Gx, Gy, Hp = Gd+/2 and
+// Hm = Gd-/2 (two-directional operators: Gx and Gy only; Hp, Hm unread).
+template <int NP, bool DIR, bool FAST, int OPR>
+__device__ __forceinline__ void store_row(const U8Job &J, int yo, int xo, bool row_ok,
+                                          const v2s (&Gx)[NP], const v2s (&Hp)[NP],
+                                          const v2s (&Gy)[NP], const v2s (&Hm)[NP])
+{
+    constexpr int PPL = 2 * NP;
+    if (!FAST && !row_ok) return;
+    const int nvalid = J.Wo - xo;          // pixels of this lane inside the image
+    if (!FAST && nvalid <= 0) return;
+    const bool full = FAST || nvalid >= PPL;
+    if (DIR ? J.mag != nullptr : true) {
+        u32 out[PPL / 4];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            // S = Gx^2 + Gy^2 + Gd^2 + Gdt^2 = Gx^2 + Gy^2 + 2 (Hp^2 + Hm^2):
+            // byte permutes pair (Gx, Gy) and (Hp, Hm) of one pixel, v_dot2
+            // squares and sums each pair.
+            const u32 xyl = perm(U2(Gy[j]), U2(Gx[j]), 0x05040100u);
+            const u32 xyh = perm(U2(Gy[j]), U2(Gx[j]), 0x07060302u);
+            int sl, sh;
+            if constexpr (OPR == kOp4x5) {
+                const u32 hhl = perm(U2(Hm[j]), U2(Hp[j]), 0x05040100u);
+                const u32 hhh = perm(U2(Hm[j]), U2(Hp[j]), 0x07060302u);
+                sl = 2 * dot2_sq(hhl) + dot2_sq(xyl);
+                sh = 2 * dot2_sq(hhh) + dot2_sq(xyh);
+            } else {
+                sl = dot2_sq(xyl);
+                sh = dot2_sq(xyh);
+            }
+            const int ql = j, qh = j + NP;   // pixel indices inside the lane
+            const float fl = mag_f(sl), fh = mag_f(sh);
+            // the first byte written into a word starts from any value: all
+            // four bytes of every word are overwritten
+            out[ql >> 2] = __builtin_amdgcn_cvt_pk_u8_f32(fl, ql & 3, (ql & 3) ? out[ql >> 2] : __builtin_bit_cast(u32, fl));
+            out[qh >> 2] = __builtin_amdgcn_cvt_pk_u8_f32(fh, qh & 3, (qh & 3) ? out[qh >> 2] : __builtin_bit_cast(u32, fh));
+        }
+        GMEM uint8_t *p = ((GMEM uint8_t *)J.mag + (int64_t)yo * J.mag_pitch) + (unsigned)xo;
+        if (FAST || full) {
+            if constexpr (PPL == 16)
+                *reinterpret_cast<GMEM gv4u_u *>(p) = gv4u{out[0], out[1], out[2], out[3]};
+            else
+                *reinterpret_cast<GMEM gv2u_u *>(p) = gv2u{out[0], out[1]};
+        } else {
+#pragma unroll
+            for (int q = 0; q < PPL; ++q)
+                if (q < nvalid) p[q] = (uint8_t)(out[q >> 2] >> (8 * (q & 3)));
+        }
+    }
+    if (DIR && J.dir_type != 0) {
+        // plane order: 0 deg Gx, 45 deg Gd, 90 deg Gy, 135 deg Gdt (the
+        // two-directional operators write planes 0 and 2)
+        v2s P[4][NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            P[0][j] = Gx[j];
+            P[2][j] = Gy[j];
+            if constexpr (OPR == kOp4x5) {
+                P[1][j] = Hp[j] + Hm[j];          // Gd  = (Gd+ + Gd-)/2 = Hp + Hm
+                P[3][j] = Hp[j] - Hm[j];          // Gdt = (Gd+ - Gd-)/2 = Hp - Hm
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (OPR != kOp4x5 && (k & 1)) continue;
+            GMEM char *base = (GMEM char *)J.dir[k] + (int64_t)yo * J.dir_pitch;
+            if (J.dir_type == 1) {
+                u32 o[NP];   // int16 pixels (2m, 2m+1)
+#pragma unroll
+                for (int m = 0; m < NP; ++m) {
+                    const int a = 2 * m;
+                    o[m] = a < NP ? perm(U2(P[k][a + 1]), U2(P[k][a]), 0x05040100u)
+                                  : perm(U2(P[k][a - NP + 1]), U2(P[k][a - NP]), 0x07060302u);
+                }
+                GMEM int16_t *p = reinterpret_cast<GMEM int16_t *>(base) + xo;
+                if (FAST || full) {
+#pragma unroll
+                    for (int m = 0; m < NP; m += 4)
+                        *reinterpret_cast<GMEM gv4u_u *>(p + 2 * m) = gv4u{o[m], o[m + 1], o[m + 2], o[m + 3]};
+                } else {
+#pragma unroll
+                    for (int q = 0; q < PPL; ++q)
+                        if (q < nvalid) p[q] = (int16_t)(o[q >> 1] >> (16 * (q & 1)));
+                }
+            } else {
+                int o[PPL];
+#pragma unroll
+                for (int j = 0; j < NP; ++j) {
+                    o[j] = P[k][j].x;
+                    o[j + NP] = P[k][j].y;
+                }
+                GMEM int32_t *p = reinterpret_cast<GMEM int32_t *>(base) + xo;
+                if (FAST || full) {
+#pragma unroll
+                    for (int q = 0; q < PPL; q += 4)
+                        *reinterpret_cast<GMEM gv4u_u *>(p + q) = gv4u{(u32)o[q], (u32)o[q + 1], (u32)o[q + 2], (u32)o[q + 3]};
+                } else {
+#pragma unroll
+                    for (int q = 0; q < PPL; ++q)
+                        if (q < nvalid) p[q] = o[q];
+                }
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+
+// What one wave sweeps: per lane the output column xo of its first pixel,
+// per 16-lane group the first output row yo0 and its row count nrow (0 for
+// an idle group); the wave walks niter rows (the largest nrow).  fix_right /
+// fix_left: the wave touches the right / left image border (replicate).
+struct Sweep {
+    int xo, yo0, nrow, niter;
+    bool fix_right, fix_left;
+};
+
+// Sweep the wave's tiles top to bottom.  FAST: every group active for all
+// niter rows, every lane's block and outputs inside the image, 16-byte
+// aligned input rows (EDGE: with the group-halo fix-ups of an image edge):
+// the loop body has no branches, so the compiler can schedule across steps.
+template <int PPL, int OFF, bool ALIGNED, bool DIR, bool FAST, bool EDGE, int OPR>
+__device__ void sweep(const U8Job &J, const Sweep &g)
+{
+    static_assert(!EDGE || FAST, "edge fix-ups by mask exist for fast waves only");
+    constexpr int NP = PPL / 2;
+    const int lane16 = threadIdx.x & 15;
+    const int xo = g.xo, yo0 = g.yo0, nrow = g.nrow, niter = g.niter;
+    const int W = J.W;
+    const int ymax = J.H - 1;
+    const int yin0 = yo0 + OFF - 2;                  // input row of window slot 0
+    const int tlast = niter + 3;                     // last input row slot needed
+
+    // load columns: the lane's aligned block and the group's outer halo dwords
+    const LoadCols lc = load_columns(xo, lane16, W, PPL);
+    const unsigned ldx = lc.ldx, hx = lc.hx;
+    const bool fix_right = FAST ? false : g.fix_right;
+    const bool fix_left = FAST ? false : g.fix_left;
+    const EdgeFix efix = edge_fix<PPL, OFF>(lane16, xo, W, EDGE && g.fix_left, EDGE && g.fix_right);
+
+    const GMEM uint8_t *src = (const GMEM uint8_t *)J.src;
+    const int64_t pitch = J.src_pitch;
+    auto rowp = [&](int t) { return src + (int64_t)clampi(yin0 + t, 0, ymax) * pitch; };
+
+    // Rings indexed by input row mod 5 (A2 and B by the row they are centred
+    // on).  Live ranges are short: an unpacked row lives 3 steps, v_s (A2) and
+    // the pair sums B 2-3 steps, the row filters 5 steps.
+    v2s Rr[5][NP + 4];
+    v2s A2r[5][NP + 4], Br[5][NP + 4];
+    v2s HR[5][NP], HS[5][NP];
+    RawRow<PPL> raw[5];
+
+    // FAST waves load a row past the end as a repeat of the last needed row
+    // (a cache hit) instead of branching around the load.
+    auto fetch = [&](int t, RawRow<PPL> &r) {
+        if constexpr (ALIGNED) load_row<PPL>(r, rowp(FAST ? min(t, tlast) : t), ldx, hx);
+    };
+    auto fetch_if = [&](int t, RawRow<PPL> &r) {
+        if (FAST || t <= tlast) fetch(t, r);
+    };
+    auto process = [&](int t, RawRow<PPL> &r, v2s (&R)[NP + 4], v2s (&hr)[NP], v2s (&hs)[NP]) {
+        Win<PPL> w;
+        if constexpr (EDGE) apply_edge<PPL>(r, efix);
+        if constexpr (ALIGNED)
+            w = finish_row<PPL, OFF>(r, lane16, xo, W, fix_right, fix_left);
+        else
+            w = load_row_bytes<PPL>(rowp(t), xo, W);
+        unpack<PPL, OFF>(w, R);
+        row_filters<NP>(R, hr, hs);
+    };
+
+    // prologue: rows t = 0..4 in flight, rows 0..3 processed (which frees
+    // their slots), then rows 5 .. 3 + kPD.  Row t always lives in raw[t % 5].
+    static_assert(kPD >= 1 && kPD <= 4, "prefetch distance must fit the 5-slot ring");
+#pragma unroll
+    for (int t = 0; t < 5; ++t) fetch_if(t, raw[t]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) process(t, raw[t], Rr[t], HR[t], HS[t]);
+#pragma unroll
+    for (int t = 5; t < 4 + kPD; ++t) fetch_if(t, raw[t % 5]);
+#pragma unroll
+    for (int c = 0; c < NP + 4; ++c) {
+        A2r[1][c] = Rr[2][c] - Rr[0][c];        // v_s centred on row 1
+        A2r[2][c] = Rr[3][c] - Rr[1][c];        // v_s centred on row 2
+        Br[2][c] = A2r[1][c] + A2r[2][c];       // B(2) = v_s(1) + v_s(2)
+    }
+
+    // step i: input row t = i + 4 enters; output row i has its centre at t - 2.
+    // v_r(y) = v_s(y-1) + 2 v_s(y) + v_s(y+1) = B(y) + B(y+1).
+    auto step = [&](int i, auto phase) {
+        constexpr int p = decltype(phase)::value;
+        constexpr int s0 = p, s1 = (p + 1) % 5, s2 = (p + 2) % 5, s3 = (p + 3) % 5, s4 = (p + 4) % 5;
+        constexpr int sp = (p + 4 + kPD) % 5;
+        fetch_if(i + 4 + kPD, raw[sp]);
+        process(i + 4, raw[s4], Rr[s4], HR[s4], HS[s4]);
+        v2s vr[NP + 4];
+#pragma unroll
+        for (int c = 0; c < NP + 4; ++c) {
+            A2r[s3][c] = Rr[s4][c] - Rr[s2][c];     // v_s(t-1)
+            Br[s3][c] = A2r[s2][c] + A2r[s3][c];    // B(t-1)
+            vr[c] = Br[s2][c] + Br[s3][c];          // v_r(t-2)
+        }
+        v2s Gx[NP], Hp[NP], Gy[NP], Hm[NP];
+        if constexpr (OPR == kOp2x3) {
+            // window rows 1..3 around the centre row; the unused row filters,
+            // pair sums and v_r are dropped by the compiler
+            responses_3x3<NP>(HS[s1], HS[s2], HS[s3], A2r[s2], Gx, Gy);
+        } else {
+            responses_y<NP>(vr, A2r[s2], Gy, Hp);
+            responses_x<NP>(HR[s0], HR[s1], HR[s2], HR[s3], HR[s4], HS[s0], HS[s2], HS[s4], Gx, Hm);
+        }
+        store_row<NP, DIR, FAST, OPR>(J, yo0 + i, xo, FAST || i < nrow, Gx, Hp, Gy, Hm);
+        // keep each row's work in its own scheduling region: interleaving
+        // rows buys little ILP and costs the registers of a second row
+        __builtin_amdgcn_sched_barrier(0);
+    };
+
+    using P0 = std::integral_constant<int, 0>;
+    using P1 = std::integral_constant<int, 1>;
+    using P2 = std::integral_constant<int, 2>;
+    using P3 = std::integral_constant<int, 3>;
+    using P4 = std::integral_constant<int, 4>;
+    // (a main loop of whole 5-step blocks plus a remainder keeps ~80 more
+    // values live across the loop exit; the uniform breaks cost two SALU ops)
+    for (int i = 0; i < niter; i += 5) {
+        step(i, P0{});
+        if (i + 1 >= niter) break;
+        step(i + 1, P1{});
+        if (i + 2 >= niter) break;
+        step(i + 2, P2{});
+        if (i + 3 >= niter) break;
+        step(i + 3, P3{});
+        if (i + 4 >= niter) break;
+        step(i + 4, P4{});
+    }
+}
+
+constexpr int kWaves = 4;   // waves per workgroup
+
+// Waves per SIMD the single-image kernel is compiled for (register budget
+// 512 / waves): 16 pixels per lane needs ~220 VGPRs (2 waves), 8 pixels per
+// lane ~134 (3 waves), or 128 with a few spilled values (4 waves).  The
+// two-directional operators keep fewer rings live.
+#ifndef SOBEL4X5_WAVES_PPL16
+#define SOBEL4X5_WAVES_PPL16 2
+#endif
+#ifndef SOBEL4X5_WAVES_PPL8
+#define SOBEL4X5_WAVES_PPL8 3
+#endif
+#ifndef SOBEL4X5_WAVES_2DIR_PPL16
+#define SOBEL4X5_WAVES_2DIR_PPL16 3
+#endif
+#ifndef SOBEL4X5_WAVES_2DIR_PPL8
+#define SOBEL4X5_WAVES_2DIR_PPL8 4
+#endif
+// (the byte-wise loads of unaligned rows and the directional stores need
+// more registers: one wave less for them)
+constexpr int single_waves(int ppl, int opr, bool aligned, bool dir)
+{
+    if (opr == kOp4x5) return ppl == 8 ? SOBEL4X5_WAVES_PPL8 : SOBEL4X5_WAVES_PPL16;
+    if (ppl == 8) return aligned ? SOBEL4X5_WAVES_2DIR_PPL8 : SOBEL4X5_WAVES_2DIR_PPL8 - 1;
+    return aligned && !dir ? SOBEL4X5_WAVES_2DIR_PPL16 : SOBEL4X5_WAVES_2DIR_PPL16 - 1;
+}
+
+// Single image.  Wave w takes tile strip w / nchunk (four tiles side by
+// side, so all groups walk the same rows and row addresses stay scalar) and
+// the (w % nchunk)-th of nchunk equal row ranges of it: every resident wave
+// gets the same amount of work and there is no tail of a second round.
+template <int PPL, int OFF, bool ALIGNED, bool DIR, int OPR>
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
+    single_waves(PPL, OPR, ALIGNED, DIR), single_waves(PPL, OPR, ALIGNED, DIR)))) void k_u8_single(U8Job J, int nchunk)
+{
+    constexpr int TW = 16 * PPL;
+    const int w = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ntxw = (J.ntx + 3) >> 2;
+    if (w >= ntxw * nchunk) return;
+    const int strip = w / nchunk, k = w % nchunk;
+    const int y0 = (int)(((int64_t)k * J.Ho) / nchunk);
+    const int y1 = (int)(((int64_t)(k + 1) * J.Ho) / nchunk);
+    if (y1 <= y0) return;
+    const int grp = (threadIdx.x >> 4) & 3;
+    const int tx = strip * 4 + grp;
+    Sweep g;
+    g.xo = tx * TW + (threadIdx.x & 15) * PPL;
+    g.yo0 = y0;
+    g.niter = y1 - y0;
+    g.nrow = tx < J.ntx ? g.niter : 0;
+    g.fix_right = (strip * 4 + 4) * TW + 4 > J.W;
+    g.fix_left = OFF == 0 && strip == 0;
+    // fast: all four tiles complete (every lane's block and output inside
+    // the image); the strips at the image edges take the fast path with mask
+    // fix-ups of their group halos
+    const bool fast = ALIGNED && (strip * 4 + 4) * TW <= J.Wo;
+    if (fast && !g.fix_right && !g.fix_left)
+        sweep<PPL, OFF, ALIGNED, DIR, true, false, OPR>(J, g);
+    else if (fast)
+        sweep<PPL, OFF, ALIGNED, DIR, true, true, OPR>(J, g);
+    else
+        sweep<PPL, OFF, ALIGNED, DIR, false, false, OPR>(J, g);
+}
+
+
+template <int PPL, int OFF, bool ALIGNED, bool DIR, int OPR>
+const void *single_fn()
+{
+    return reinterpret_cast<const void *>(&k_u8_single<PPL, OFF, ALIGNED, DIR, OPR>);
+}
+
+// Resident waves of a kernel on this device (cached per kernel).
+int resident_waves(const void *fn)
+{
+    static std::mutex mu;
+    static std::vector<std::pair<const void *, int>> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto &e : cache)
+        if (e.first == fn) return e.second;
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * kWaves, 0) != hipSuccess)
+        return 0;
+    const int w = std::max(1, per_cu) * ncu * kWaves;
+    cache.emplace_back(fn, w);
+    return w;
+}
+
+template <int PPL, int OFF, bool DIR, int OPR>
+hipError_t launch_single_t(const U8Job &j, const U8Shape &s, hipStream_t st)
+{
+    const bool aligned = u8_rows_aligned(j);
+    const void *fn = aligned ? single_fn<PPL, OFF, true, DIR, OPR>() : single_fn<PPL, OFF, false, DIR, OPR>();
+    const int ntxw = (j.ntx + 3) / 4;
+    int slots = s.waves > 0 ? s.waves : resident_waves(fn);
+    if (slots <= 0) slots = 2048;
+    // equal row ranges per strip, at least 8 rows each
+    int nchunk = std::max(1, slots / std::max(1, ntxw));
+    nchunk = std::min(nchunk, std::max(1, j.Ho / 8));
+    const int64_t waves = (int64_t)ntxw * nchunk;
+    const int grid = (int)((waves + kWaves - 1) / kWaves);
+    U8Job jj = j;
+    void *args[] = {(void *)&jj, (void *)&nchunk};
+    return hipLaunchKernel(fn, dim3(grid), dim3(64 * kWaves), args, 0, st);
+}
+
+}  // namespace
+}  // namespace s4x5

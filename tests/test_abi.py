@@ -76,6 +76,40 @@ def test_validate_u8(sobel_lib):
     assert isinstance(msg, str)
 
 
+def v_op(api, op, src=FAKE, w=64, h=32, pitch=64, border=0, mag=FAKE + (1 << 24), mag_pitch=64,
+         dir_type=0, dirs=None, dir_pitch=0):
+    out = api.Outputs()
+    out.mag = mag
+    out.mag_pitch = mag_pitch
+    out.dir_type = dir_type
+    out.dir_pitch = dir_pitch
+    for k in range(4):
+        out.dir[k] = (dirs[k] if dirs else 0)
+    return api.lib.sobel4x5_validate_u8_op(src, w, h, pitch, op, border, ctypes.byref(out))
+
+
+def test_validate_u8_op(sobel_lib):
+    api = sobel_lib
+    for op in (0, 1, 2):
+        assert v_op(api, op) == 0
+    assert v_op(api, 3) == api.EINVAL
+    assert v_op(api, -1) == api.EINVAL
+    # VALID: the 3x3 pair needs 3x3 and shrinks by 2, the 5x5 operators need 5x5
+    assert v_op(api, 2, border=1, w=3, h=3, pitch=3, mag_pitch=1) == 0
+    assert v_op(api, 2, border=1, w=2, h=3, pitch=3, mag_pitch=1) == api.EINVAL
+    assert v_op(api, 1, border=1, w=4, h=5, pitch=5, mag_pitch=1) == api.EINVAL
+    assert v_op(api, 2, border=1, w=10, h=4, pitch=10, mag_pitch=8) == 0
+    assert v_op(api, 2, border=1, w=10, h=4, pitch=10, mag_pitch=7) == api.EINVAL
+    # two-directional operators read dir[0] and dir[2] only
+    dirs = [FAKE + (k + 2) * (1 << 24) for k in range(4)]
+    two = [dirs[0], 0, dirs[2], 0]
+    assert v_op(api, 1, mag=0, dir_type=1, dirs=two, dir_pitch=128) == 0
+    assert v_op(api, 2, mag=0, dir_type=2, dirs=two, dir_pitch=256) == 0
+    assert v_op(api, 0, mag=0, dir_type=1, dirs=two, dir_pitch=128) == api.EINVAL
+    assert v_op(api, 2, mag=0, dir_type=1, dirs=[dirs[0], 0, 0, 0], dir_pitch=128) == api.EINVAL
+    assert v_op(api, 2, mag=0, dir_type=1, dirs=[dirs[0], 0, dirs[0], 0], dir_pitch=128) == api.EINVAL
+
+
 def test_validate_batch(sobel_lib):
     api = sobel_lib
     arr = (api.Image * 3)()
