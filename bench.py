@@ -133,12 +133,39 @@ def bench_sweep(torch, api, synth, dev, steps, warmup):
     return out
 
 
+def time_graph(torch, fn, k, reps):
+    """Average ms per launch of fn(i), i < k, captured once into a graph and
+    replayed `reps` times: the device-side rate without the host's per-call
+    cost (which exceeds the kernel time for small images)."""
+    for i in range(min(k, 3)):
+        fn(i)                      # per-kernel set-up (occupancy queries) outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for i in range(k):
+            fn(i)
+    g.replay()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        g.replay()
+    e1.record(s)
+    torch.cuda.synchronize()
+    del g
+    return e0.elapsed_time(e1) / (k * reps)
+
+
 def bench_ops(torch, api, synth, dev, steps, warmup):
     """The paper's operator comparison (Sec. 5, Table 1: its four-directional
     5x5 kernel against the 3x3 operator) on this GPU: the four-directional
     5x5 operator, its 0 / 90 deg pair alone, and the two-directional 3x3
     Sobel pair, uint8 magnitude only, replicate border, at Table 1's sizes
-    and at 8192^2."""
+    and at 8192^2.  Each entry: a graph of back-to-back launches over
+    rotating buffers, replayed; `launch_us` is the same with one host call
+    per launch."""
     names = {api.OP_4DIR_5X5: "4dir_5x5", api.OP_2DIR_5X5: "2dir_5x5", api.OP_2DIR_3X3: "2dir_3x3"}
     out = {}
     for n in (512, 1024, 2048, 8192):
@@ -151,17 +178,17 @@ def bench_ops(torch, api, synth, dev, steps, warmup):
         row = {}
         for op, name in names.items():
             fn = lambda i, op=op: api.sobel4x5_u8_op(srcs[i % nsets], op, mag=mags[i % nsets])
-            k = max(20, steps * (4 if n <= 2048 else 1))
-            ms = time_launches(torch, fn, k, max(5, warmup))
+            k = min(nsets, 200) if n <= 2048 else nsets
+            reps = max(2, steps // 10) if n <= 2048 else max(2, steps // k)
+            ms = time_graph(torch, fn, k, reps)
+            launch_ms = time_launches(torch, fn, max(20, steps), max(5, warmup))
             gbs = 2 * px / (ms * 1e-3) / 1e9
             row[name] = {"us": round(ms * 1e3, 3), "gpx_per_s": round(px / (ms * 1e-3) / 1e9, 2),
-                         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+                         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "launch_us": round(launch_ms * 1e3, 3)}
         row["time_ratio_4dir5x5_over_2dir3x3"] = round(row["4dir_5x5"]["us"] / row["2dir_3x3"]["us"], 3)
         out["%d" % n] = row
         del srcs, mags, base
         torch.cuda.empty_cache()
-    out["note"] = ("back-to-back launches timed with HIP events over rotating buffers (>= 1 GiB); "
-                   "below 2048^2 a launch lasts a few microseconds, so launch gaps weigh in")
     return out
 
 

@@ -166,8 +166,9 @@ int env_int(const char *name, int dflt)
 
 // Shape for one image: 16 pixels per lane when a strip of four 256-column
 // tiles is mostly inside the image, else 8; directional outputs use 8 (their
-// kernel keeps more values live).  SOBEL4X5_U8_PPL (8 or 16) and
-// SOBEL4X5_U8_WAVES (waves to launch) override the choice for tuning runs.
+// kernel keeps more values live).  SOBEL4X5_U8_PPL (8 or 16),
+// SOBEL4X5_U8_WAVES (waves to launch) and SOBEL4X5_U8_MIN_ROWS (fewest rows
+// per wave) override the choice for tuning runs.
 U8Shape default_shape(int32_t Wo, int32_t Ho, int32_t dir_type)
 {
     (void)Ho;
@@ -178,6 +179,8 @@ U8Shape default_shape(int32_t Wo, int32_t Ho, int32_t dir_type)
     s.th = 32;
     s.wpg = 4;
     s.waves = env_int("SOBEL4X5_U8_WAVES", 0);
+    const int mr = env_int("SOBEL4X5_U8_MIN_ROWS", 0);
+    if (mr >= 1 && mr <= 64) s.min_rows = mr;
     return s;
 }
 
