@@ -23,6 +23,8 @@ _LIB = _HERE / "liboracle.so"
 
 REPLICATE = 0
 VALID = 1
+ZERO = 2           # pixels outside the image read 0 (uint8 path)
+REFLECT101 = 3     # mirror about the edge pixel without repeating it (uint8 path)
 
 _lib = None
 
@@ -81,7 +83,7 @@ def _weights_arg(weights):
 
 
 def out_shape(h: int, w: int, border: int):
-    return (h, w) if border == REPLICATE else (h - 4, w - 4)
+    return (h - 4, w - 4) if border == VALID else (h, w)
 
 
 def weights() -> np.ndarray:
@@ -128,7 +130,7 @@ def sobel_u8_2dir(img: np.ndarray, size: int, border: int = REPLICATE, *,
         raise ValueError("img must be a 2-D uint8 array with unit column stride")
     h, w = img.shape
     r = size // 2
-    ho, wo = (h, w) if border == REPLICATE else (h - 2 * r, w - 2 * r)
+    ho, wo = (h - 2 * r, w - 2 * r) if border == VALID else (h, w)
     mag = np.empty((max(ho, 0), max(wo, 0)), np.uint8) if want_mag else None
     d = np.empty((2, max(ho, 0), max(wo, 0)), np.int32) if want_dir else None
     rc = _load().oracle_u8_2dir(img.ctypes.data_as(ctypes.c_void_p), w, h, img.strides[0], border,

@@ -23,7 +23,9 @@
  *     the pixels in Sec. 4.3);
  *   - border REPLICATE (clamp-to-edge) keeps the output at HxW; border VALID
  *     is the paper-native shrink by 2r = 4 rows and columns (Sec. 4.3, data
- *     flow), out(y, x) = full(y + 2, x + 2);
+ *     flow), out(y, x) = full(y + 2, x + 2); the uint8 path also offers ZERO
+ *     (pixels outside read 0) and REFLECT101 (mirror about the edge pixel,
+ *     see border_index), both H x W;
  *   - the uint8 magnitude is min(255, round-to-nearest(sqrt(S))), computed
  *     exactly in integers (ties cannot occur for integer S);
  *   - the real-valued path (not in the paper) is the same correlation in fp64,
@@ -52,6 +54,8 @@ static int omp_default_threads(void) { return 1; }
 
 #define OR_BORDER_REPLICATE 0
 #define OR_BORDER_VALID 1
+#define OR_BORDER_ZERO 2
+#define OR_BORDER_REFLECT101 3
 
 /* Eq. (sobel5_1), typed in row by row from the printed matrices, in plane
  * order 0 deg (Gx), 45 deg (Gd), 90 deg (Gy), 135 deg (Gdt). */
@@ -102,6 +106,41 @@ static inline long clampl(long v, long lo, long hi)
     return v < lo ? lo : (v > hi ? hi : v);
 }
 
+/*
+ * Index of the pixel that stands in for position i of an axis of n pixels
+ * (0 <= i < n maps to itself), or -1 where the border reads zero.
+ *   REPLICATE / VALID : the nearest pixel (clamp to [0, n-1]);
+ *   ZERO              : -1 (the pixel reads 0);
+ *   REFLECT101        : the mirror image about the edge pixel, without
+ *                       repeating it (..., 2, 1 | 0, 1, ..., n-1 | n-2, ...),
+ *                       applied until the index lands inside: the extended
+ *                       axis is periodic with period 2(n-1); n = 1 gives 0.
+ */
+static long border_index(long i, long n, int border)
+{
+    if (i >= 0 && i < n)
+        return i;
+    if (border == OR_BORDER_ZERO)
+        return -1;
+    if (border == OR_BORDER_REFLECT101) {
+        if (n == 1)
+            return 0;
+        const long p = 2 * (n - 1);
+        long m = i % p;
+        if (m < 0)
+            m += p;
+        return m < n ? m : p - m;
+    }
+    return clampl(i, 0, n - 1);
+}
+
+/* Pixel value at (y, x) under the border rule. */
+static inline int64_t pixel_u8(const uint8_t *src, int W, int H, long pitch, int border, long y, long x)
+{
+    const long yy = border_index(y, H, border), xx = border_index(x, W, border);
+    return (yy < 0 || xx < 0) ? 0 : (int64_t)src[yy * pitch + xx];
+}
+
 /* round(sqrt(S)) for S >= 0, exactly, by integer square root.
  * r = floor(sqrt(S)); sqrt(S) >= r + 1/2  <=>  S > r*r + r (S integer). */
 static int64_t round_sqrt_i64(int64_t S)
@@ -116,11 +155,13 @@ static int64_t round_sqrt_i64(int64_t S)
 
 int64_t oracle_round_sqrt(int64_t S) { return S < 0 ? -1 : round_sqrt_i64(S); }
 
+/* Output size under a border rule (the real-valued path takes REPLICATE and
+ * VALID only). */
 static int out_dims(int W, int H, int border, int *Wo, int *Ho)
 {
     if (W <= 0 || H <= 0)
         return OR_EINVAL;
-    if (border == OR_BORDER_REPLICATE) {
+    if (border == OR_BORDER_REPLICATE || border == OR_BORDER_ZERO || border == OR_BORDER_REFLECT101) {
         *Wo = W;
         *Ho = H;
     } else if (border == OR_BORDER_VALID) {
@@ -145,13 +186,9 @@ static void responses_u8(const uint8_t *src, int W, int H, long pitch, int borde
     }
     for (int k = 0; k < 4; ++k) {
         int64_t acc = 0;
-        for (int i = 0; i < 5; ++i) {
-            long yy = clampl(yc + i - 2, 0, H - 1);
-            for (int j = 0; j < 5; ++j) {
-                long xx = clampl(xc + j - 2, 0, W - 1);
-                acc += (int64_t)K[(k * 5 + i) * 5 + j] * (int64_t)src[yy * pitch + xx];
-            }
-        }
+        for (int i = 0; i < 5; ++i)
+            for (int j = 0; j < 5; ++j)
+                acc += (int64_t)K[(k * 5 + i) * 5 + j] * pixel_u8(src, W, H, pitch, border, yc + i - 2, xc + j - 2);
         G[k] = acc;
     }
 }
@@ -274,7 +311,7 @@ int oracle_f64_fwd(const double *x, int B, int H, int W, int border,
                    double *mag, double *dir, const int32_t *weights, int nthreads)
 {
     int Wo, Ho;
-    if (!x || B < 0 || out_dims(W, H, border, &Wo, &Ho) != OR_OK)
+    if (!x || B < 0 || border > OR_BORDER_VALID || out_dims(W, H, border, &Wo, &Ho) != OR_OK)
         return OR_EINVAL;
     const int32_t *K = pick_weights(weights);
     const long plane_in = (long)W * H, plane_out = (long)Wo * Ho;
@@ -311,7 +348,7 @@ static int bwd_impl(const double *x, const double *g, int B, int H, int W, int b
                     double *dx, const int32_t *weights, int nthreads, int absmode)
 {
     int Wo, Ho;
-    if (!x || !g || !dx || B < 0 || out_dims(W, H, border, &Wo, &Ho) != OR_OK)
+    if (!x || !g || !dx || B < 0 || border > OR_BORDER_VALID || out_dims(W, H, border, &Wo, &Ho) != OR_OK)
         return OR_EINVAL;
     const int32_t *K = pick_weights(weights);
     const long plane_in = (long)W * H, plane_out = (long)Wo * Ho;
@@ -373,7 +410,7 @@ int oracle_f64_fwd_scale(const double *x, int B, int H, int W, int border, doubl
                          const int32_t *weights, int nthreads)
 {
     int Wo, Ho;
-    if (!x || !scale || B < 0 || out_dims(W, H, border, &Wo, &Ho) != OR_OK)
+    if (!x || !scale || B < 0 || border > OR_BORDER_VALID || out_dims(W, H, border, &Wo, &Ho) != OR_OK)
         return OR_EINVAL;
     const int32_t *K = pick_weights(weights);
     const long plane_in = (long)W * H, plane_out = (long)Wo * Ho;
@@ -446,7 +483,7 @@ int oracle_u8_2dir(const uint8_t *src, int W, int H, long pitch, int border, int
             return OR_EINVAL;
         Wo = W - 2 * r;
         Ho = H - 2 * r;
-    } else if (border != OR_BORDER_REPLICATE) {
+    } else if (border != OR_BORDER_REPLICATE && border != OR_BORDER_ZERO && border != OR_BORDER_REFLECT101) {
         return OR_EINVAL;
     }
     if (mag && mag_pitch < Wo)
@@ -461,11 +498,9 @@ int oracle_u8_2dir(const uint8_t *src, int W, int H, long pitch, int border, int
             for (int k = 0; k < 2; ++k) {
                 int64_t acc = 0;
                 for (int i = 0; i < size; ++i) {
-                    const long yy = clampl(yc + i - r, 0, H - 1);
                     for (int j = 0; j < size; ++j) {
-                        const long xx = clampl(xc + j - r, 0, W - 1);
                         const int32_t w = size == 3 ? K3_PAPER[k][i][j] : K_PAPER[2 * k][i][j];
-                        acc += (int64_t)w * (int64_t)src[yy * pitch + xx];
+                        acc += (int64_t)w * pixel_u8(src, W, H, pitch, border, yc + i - r, xc + j - r);
                     }
                 }
                 G[k] = acc;
