@@ -34,6 +34,16 @@
  *   SOBEL4X5_BORDER_VALID     : the paper's shrink by 2r = 4 (Sec. 4.3, data
  *                               flow); output is (H-4) x (W-4) and
  *                               out(y, x) = replicate(y+2, x+2); H, W >= 5.
+ *   SOBEL4X5_BORDER_ZERO      : pixels outside the image read 0; H x W.
+ *   SOBEL4X5_BORDER_REFLECT101: pixels outside the image read their mirror
+ *                               image about the edge pixel, which is not
+ *                               repeated (index -1 -> 1, -2 -> 2, W -> W-2,
+ *                               W+1 -> W-3); an axis of 1 or 2 pixels
+ *                               reflects again until the index lands inside
+ *                               (period 2(n-1)).  H x W; any H, W >= 1.
+ *   ZERO and REFLECT101 serve the uint8 entry points (single, operators,
+ *   run-time weights, batched, pipeline); the fp32 pair returns
+ *   SOBEL4X5_EUNSUPPORTED for them.
  *
  * uint8 magnitude: min(255, round-to-nearest(sqrt(S))), S = Gx^2 + Gd^2 +
  * Gy^2 + Gdt^2 -- exact (integer S never sits on a half-way point).
@@ -47,7 +57,7 @@
 extern "C" {
 #endif
 
-#define SOBEL4X5_VERSION 100
+#define SOBEL4X5_VERSION 110
 
 /* status codes */
 #define SOBEL4X5_OK 0
@@ -59,6 +69,8 @@ extern "C" {
 /* border rules */
 #define SOBEL4X5_BORDER_REPLICATE 0
 #define SOBEL4X5_BORDER_VALID 1
+#define SOBEL4X5_BORDER_ZERO 2
+#define SOBEL4X5_BORDER_REFLECT101 3
 
 /* directional output element types */
 #define SOBEL4X5_DIR_NONE 0
@@ -223,6 +235,21 @@ int sobel4x5_batched(const sobel4x5_image *imgs, int32_t count, int32_t border, 
 
 /* Host-only argument check of a batch (never touches the GPU). */
 int sobel4x5_validate_batch(const sobel4x5_image *imgs, int32_t count, int32_t border);
+
+/*
+ * Batches with per-image outputs: the calls above with `outs`, a HOST array
+ * of `count` sobel4x5_outputs (copied), image i writing outs[i] -- its
+ * magnitude (mag may be NULL) and/or its directional planes (dir_type, four
+ * planes, as for sobel4x5_u8).  imgs[i].mag and mag_pitch are ignored.
+ * outs == NULL is the plain call.  Outputs of all images must not overlap
+ * each other or any input.  The autotuner checks every output plane.
+ */
+int sobel4x5_plan_create_ex(const sobel4x5_image *imgs, const sobel4x5_outputs *outs, int32_t count,
+                            int32_t border, uint32_t flags, sobel4x5_plan *out);
+int sobel4x5_batched_ex(const sobel4x5_image *imgs, const sobel4x5_outputs *outs, int32_t count,
+                        int32_t border, void *stream);
+int sobel4x5_validate_batch_ex(const sobel4x5_image *imgs, const sobel4x5_outputs *outs, int32_t count,
+                               int32_t border);
 
 /*
  * Host pipeline: uint8 images in HOST memory -> magnitudes in HOST memory.

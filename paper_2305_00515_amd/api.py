@@ -22,6 +22,8 @@ LIB_PATH = Path(os.environ.get("SOBEL4X5_LIBRARY") or (_PKG / "libsobel4x5.so"))
 
 BORDER_REPLICATE = 0
 BORDER_VALID = 1
+BORDER_ZERO = 2          # pixels outside the image read 0 (uint8 path)
+BORDER_REFLECT101 = 3    # mirror about the edge pixel, not repeating it (uint8 path)
 DIR_NONE = 0
 DIR_S16 = 1
 DIR_S32 = 2
@@ -69,6 +71,9 @@ def _load() -> ctypes.CDLL:
         "sobel4x5_plan_destroy": [P],
         "sobel4x5_batched": [ctypes.POINTER(Image), I32, I32, P],
         "sobel4x5_validate_batch": [ctypes.POINTER(Image), I32, I32],
+        "sobel4x5_plan_create_ex": [ctypes.POINTER(Image), ctypes.POINTER(Outputs), I32, I32, U32, ctypes.POINTER(P)],
+        "sobel4x5_batched_ex": [ctypes.POINTER(Image), ctypes.POINTER(Outputs), I32, I32, P],
+        "sobel4x5_validate_batch_ex": [ctypes.POINTER(Image), ctypes.POINTER(Outputs), I32, I32],
         "sobel4x5_f32_fwd": [P, I32, I32, I32, I64, I64, I32, P, I64, I64, P],
         "sobel4x5_f32_bwd": [P, I64, I64, P, I64, I64, I32, I32, I32, I32, P, I64, I64, P],
         "sobel4x5_validate_f32": [P, I32, I32, I32, I64, I64, I32, P, I64, I64],
@@ -121,7 +126,7 @@ def _rows(t: torch.Tensor, name: str):
 
 def out_shape(h: int, w: int, border: int, op: int = OP_4DIR_5X5):
     r = 1 if op == OP_2DIR_3X3 else 2
-    return (h, w) if border == BORDER_REPLICATE else (h - 2 * r, w - 2 * r)
+    return (h - 2 * r, w - 2 * r) if border == BORDER_VALID else (h, w)
 
 
 def _u8_outputs(src, border, mag, want_mag, dir_type, dirs, op=OP_4DIR_5X5):
@@ -304,6 +309,30 @@ def _images(srcs, mags, border):
     return arr
 
 
+def _images_ex(srcs, mags, border, want_mag, dir_type, dirs):
+    """Descriptor and per-image outputs arrays for a batch with directional
+    planes; returns (imgs, outs, [(mag or None, planes or None)])."""
+    n = len(srcs)
+    if not n:
+        raise ValueError("need at least one source")
+    mags = list(mags) if mags is not None else [None] * n
+    dirs = list(dirs) if dirs is not None else [None] * n
+    if len(mags) != n or len(dirs) != n:
+        raise ValueError("srcs, mags and dirs differ in length")
+    imgs = (Image * n)()
+    outs = (Outputs * n)()
+    res = []
+    for i, s in enumerate(srcs):
+        o, (h, w, p), r = _u8_outputs(s, border, mags[i], want_mag, dir_type, dirs[i])
+        outs[i] = o
+        imgs[i].src = s.data_ptr()
+        imgs[i].width = w
+        imgs[i].height = h
+        imgs[i].src_pitch = p
+        res.append(r)
+    return imgs, outs, res
+
+
 class Plan:
     """A reusable batched plan over fixed (src, mag) tensor pairs.
 
@@ -312,14 +341,25 @@ class Plan:
     """
 
     def __init__(self, srcs, mags, border: int = BORDER_REPLICATE, autotune: bool = False,
-                 graph: bool = True):
-        self._keep = (list(srcs), list(mags))
-        self._arr = _images(self._keep[0], self._keep[1], border)
-        self.device = self._keep[0][0].device
+                 graph: bool = True, dir_type: int = DIR_NONE, dirs=None):
+        """With dir_type, `dirs` holds each image's four planes (mags entries
+        may then be None for no magnitude)."""
+        self.device = list(srcs)[0].device
         flags = (PLAN_AUTOTUNE if autotune else 0) | (0 if graph else PLAN_NO_GRAPH)
         h = ctypes.c_void_p()
-        _check(lib.sobel4x5_plan_create(self._arr, len(self._arr), border, flags, ctypes.byref(h)),
-               "sobel4x5_plan_create")
+        if dir_type == DIR_NONE:
+            self._keep = (list(srcs), list(mags))
+            self._arr = _images(self._keep[0], self._keep[1], border)
+            _check(lib.sobel4x5_plan_create(self._arr, len(self._arr), border, flags, ctypes.byref(h)),
+                   "sobel4x5_plan_create")
+        else:
+            want = [m is not None for m in mags]
+            if len(set(want)) != 1:
+                raise ValueError("give a magnitude for every image or for none")
+            self._arr, self._outs, res = _images_ex(list(srcs), mags, border, want[0], dir_type, dirs)
+            self._keep = (list(srcs), res)
+            _check(lib.sobel4x5_plan_create_ex(self._arr, self._outs, len(self._arr), border, flags,
+                                               ctypes.byref(h)), "sobel4x5_plan_create_ex")
         self._h = h
 
     def launch(self) -> None:
@@ -346,8 +386,17 @@ class Plan:
             pass
 
 
-def sobel4x5_batched(srcs, mags=None, border: int = BORDER_REPLICATE):
-    """Magnitudes of many uint8 images of uneven sizes in one persistent launch."""
+def sobel4x5_batched(srcs, mags=None, border: int = BORDER_REPLICATE, *, want_mag: bool = True,
+                     dir_type: int = DIR_NONE, dirs=None):
+    """Magnitudes of many uint8 images of uneven sizes in one persistent launch.
+
+    With dir_type (DIR_S16 / DIR_S32) every image also gets its four
+    directional planes, and the result is a list of (mag or None, [planes]).
+    """
+    if dir_type != DIR_NONE or not want_mag:
+        imgs, outs, res = _images_ex(list(srcs), mags, border, want_mag, dir_type, dirs)
+        _check(lib.sobel4x5_batched_ex(imgs, outs, len(imgs), border, _stream(srcs[0])), "sobel4x5_batched_ex")
+        return res
     if mags is None:
         mags = []
         for s in srcs:

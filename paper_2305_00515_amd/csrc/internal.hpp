@@ -48,25 +48,28 @@ bool u8_rows_aligned(const U8Job &j);
 void u8_tile(U8Job &j, const U8Shape &s);
 
 // Single image: one launch; every resident wave takes an equal row range of
-// one strip of four tiles.
-hipError_t launch_u8_single(const U8Job &j, int border_valid, const U8Shape &s,
-                            hipStream_t stream);
+// one strip of four tiles.  `border` is the public SOBEL4X5_BORDER_* code
+// (replicate 0, valid 1, zero 2, reflect-101 3); the zero and reflect-101
+// kernels live in their own translation unit (launch_u8_single_zr).
+hipError_t launch_u8_single(const U8Job &j, int border, const U8Shape &s, hipStream_t stream);
+hipError_t launch_u8_single_zr(const U8Job &j, int border, const U8Shape &s, hipStream_t stream);
 
 // Two-directional operators on the single-image sweep: op 1 = the 0 / 90 deg
 // filters of the 5x5 operator, op 2 = the 3x3 pair (VALID: off = 1).  The
 // job's Wo, Ho and tiling are those of the operator's own border rule.
-hipError_t launch_u8_2dir(const U8Job &j, int op, int border_valid, const U8Shape &s,
-                          hipStream_t stream);
+hipError_t launch_u8_2dir(const U8Job &j, int op, int border, const U8Shape &s, hipStream_t stream);
+hipError_t launch_u8_2dir_zr(const U8Job &j, int op, int border, const U8Shape &s, hipStream_t stream);
 
-// Batched persistent launch (`aligned`: every image has 16-byte aligned src
-// rows).  `jobs` (device) holds the images; `tiles` (device, `total`
-// entries) lists every wave-tile of the batch as {image, kind | rows << 1, tx, y0}
+// Batched persistent launch (`aligned`: every image may take the vector
+// path: 16-byte aligned src rows, and at least 3 columns under reflect-101).
+// `jobs` (device) holds the images; `tiles` (device, `total` entries) lists
+// every wave-tile of the batch as {image, kind | rows << 1, tx, y0}
 // (batched_tiles); `queue` (device, 2 words, zero before the first launch)
 // is the work counter and the exit counter, reset by the last wave to
-// finish.
-hipError_t launch_u8_batched(const U8Job *jobs, const int4 *tiles, int32_t total, uint32_t *queue,
-                             int border_valid, bool aligned, const U8Shape &s, int grid,
-                             hipStream_t stream);
+// finish.  `border`: the public code; `dir`: some job asks for directional
+// planes.
+hipError_t launch_u8_batched(const U8Job *jobs, const int4 *tiles, int32_t total, uint32_t *queue, int border,
+                             bool aligned, bool dir, const U8Shape &s, int grid, hipStream_t stream);
 
 // Wave-tiles of image `img` (tiled by u8_tile with th rows per tile): the
 // complete four-tile strips side by side (kind 0) in tall row chunks
@@ -77,7 +80,7 @@ void batched_tiles(const U8Job &j, int32_t img, int th, std::vector<int4> &first
 
 // Number of workgroups of the persistent kernel that fit on the device at
 // once for shape `s` (occupancy x CUs), or 0 on error.
-int u8_persistent_grid(const U8Shape &s, int border_valid, bool aligned);
+int u8_persistent_grid(const U8Shape &s, int border, bool aligned, bool dir);
 
 // uint8 operator with run-time weights (four integer kernels that are
 // antisymmetric under a half turn), as coefficients of the 12 upper-half
@@ -89,7 +92,8 @@ struct WJob {
     void *dir[4];          // used iff dir_type != 0
     int64_t src_pitch, mag_pitch, dir_pitch;
     int32_t W, H, Wo, Ho;
-    int32_t off;           // 0 replicate, 2 valid
+    int32_t off;           // 0 replicate / zero / reflect-101, 2 valid
+    int32_t bmode;         // pixels outside the image: 0 nearest, 1 zero, 2 reflect-101
     int32_t dir_type;      // 0 none, 1 int16, 2 int32
     int32_t coef[4][12];
 };

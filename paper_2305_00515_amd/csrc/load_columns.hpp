@@ -1,6 +1,7 @@
 // Byte columns a lane of the uint8 kernels loads from every row it reads
-// (aligned-row path).  Plain integer code, shared by the kernels and by a
-// host-side check that enumerates every lane of every launch geometry.
+// (aligned-row path), and the reflect-101 index map.  Plain integer code,
+// shared by the kernels and by host-side checks that enumerate every lane of
+// every launch geometry and every index the map can be asked for.
 //
 // A lane owns ppl (8 or 16) consecutive pixels starting at column xo (a
 // multiple of ppl); it loads the aligned ppl-byte block at `ldx`, and the
@@ -42,6 +43,24 @@ S4X5_HD inline LoadCols load_columns(int xo, int lane16, int W, int ppl)
     else
         c.hx = c.ldx;
     return c;
+}
+
+// Reflect-101 border: the index that stands in for position i of an axis of
+// n >= 1 pixels, mirroring about the edge pixel without repeating it
+// (..., 2, 1 | 0, 1, ..., n-1 | n-2, ...).  The extended axis is periodic
+// with period 2(n-1); n = 1 maps everything to 0.  One reflection suffices
+// for the 5x5 operator's reach (|i - edge| <= 2) once n >= 3; the general
+// fold serves narrower axes.  The result always lies in [0, n-1].
+S4X5_HD inline int reflect101(int i, int n)
+{
+    if (i >= 0 && i < n) return i;
+    if (n == 1) return 0;
+    const int p = 2 * (n - 1);
+    if (i < 0 && -i < n) return -i;
+    if (i >= n && p - i >= 0) return p - i;
+    int m = i % p;
+    if (m < 0) m += p;
+    return m < n ? m : p - m;
 }
 
 }  // namespace s4x5

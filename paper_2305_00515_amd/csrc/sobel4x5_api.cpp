@@ -49,8 +49,10 @@ constexpr int64_t kMaxDim = 1 << 30;
 // Output size of an operator of radius r (2 for the 5x5 filters, 1 for 3x3).
 int out_dims_r(int32_t W, int32_t H, int32_t border, int r, int32_t *Wo, int32_t *Ho)
 {
-    if (border != SOBEL4X5_BORDER_REPLICATE && border != SOBEL4X5_BORDER_VALID)
-        return fail(SOBEL4X5_EINVAL, "border must be REPLICATE (0) or VALID (1), got %d", border);
+    if (border != SOBEL4X5_BORDER_REPLICATE && border != SOBEL4X5_BORDER_VALID && border != SOBEL4X5_BORDER_ZERO &&
+        border != SOBEL4X5_BORDER_REFLECT101)
+        return fail(SOBEL4X5_EINVAL, "border must be REPLICATE (0), VALID (1), ZERO (2) or REFLECT101 (3), got %d",
+                    border);
     if (W < 1 || H < 1) return fail(SOBEL4X5_EINVAL, "width and height must be >= 1 (got %d x %d)", W, H);
     if (W > kMaxDim || H > kMaxDim) return fail(SOBEL4X5_EINVAL, "image too large");
     if (border == SOBEL4X5_BORDER_VALID) {
@@ -200,31 +202,44 @@ int check_f32_buf(const char *name, const float *p, int32_t batch, int32_t cols,
     return ok();
 }
 
-int validate_batch(const sobel4x5_image *imgs, int32_t count, int32_t border)
+// Outputs of batch image i: outs[i] when given, else the image's own mag.
+sobel4x5_outputs batch_outputs(const sobel4x5_image *imgs, const sobel4x5_outputs *outs, int32_t i)
+{
+    if (outs) return outs[i];
+    sobel4x5_outputs o;
+    std::memset(&o, 0, sizeof o);
+    o.mag = imgs[i].mag;
+    o.mag_pitch = imgs[i].mag_pitch;
+    return o;
+}
+
+// Memory ranges every output of one image writes.
+void output_ranges(const sobel4x5_outputs &o, int32_t Wo, int32_t Ho, std::vector<Range> &v)
+{
+    if (o.mag) v.push_back(span(o.mag, Ho, o.mag_pitch, Wo));
+    if (o.dir_type != SOBEL4X5_DIR_NONE) {
+        const int64_t es = o.dir_type == SOBEL4X5_DIR_S16 ? 2 : 4;
+        for (int k = 0; k < 4; ++k) v.push_back(span(o.dir[k], Ho, o.dir_pitch, (int64_t)Wo * es));
+    }
+}
+
+int validate_batch(const sobel4x5_image *imgs, const sobel4x5_outputs *outs_in, int32_t count, int32_t border)
 {
     if (!imgs) return fail(SOBEL4X5_EINVAL, "imgs is NULL");
     if (count < 1) return fail(SOBEL4X5_EINVAL, "count must be >= 1 (got %d)", count);
+    std::vector<Range> outs;
     for (int32_t i = 0; i < count; ++i) {
         const sobel4x5_image &m = imgs[i];
+        const sobel4x5_outputs o = batch_outputs(imgs, outs_in, i);
+        if (!outs_in && !m.mag) return fail(SOBEL4X5_EINVAL, "image %d: mag is NULL", i);
         int32_t Wo, Ho;
-        if (out_dims(m.width, m.height, border, &Wo, &Ho))
+        if (validate_u8(m.src, m.width, m.height, m.src_pitch, border, &o, &Wo, &Ho))
             return fail(SOBEL4X5_EINVAL, "image %d: %s", i, g_last_error.c_str());
-        if (!m.src || !m.mag) return fail(SOBEL4X5_EINVAL, "image %d: src or mag is NULL", i);
-        if (check_pitch("src", m.src_pitch, m.width, m.height) ||
-            check_pitch("mag", m.mag_pitch, Wo, Ho))
-            return fail(SOBEL4X5_EINVAL, "image %d: %s", i, g_last_error.c_str());
-        if (overlap(span(m.src, m.height, m.src_pitch, m.width), span(m.mag, Ho, m.mag_pitch, Wo)))
-            return fail(SOBEL4X5_EINVAL, "image %d: mag overlaps src", i);
+        output_ranges(o, Wo, Ho, outs);
     }
     // outputs of different images must not overlap each other (sorted sweep)
-    std::vector<Range> outs(count);
-    for (int32_t i = 0; i < count; ++i) {
-        int32_t Wo, Ho;
-        out_dims(imgs[i].width, imgs[i].height, border, &Wo, &Ho);
-        outs[i] = span(imgs[i].mag, Ho, imgs[i].mag_pitch, Wo);
-    }
     std::sort(outs.begin(), outs.end(), [](const Range &a, const Range &b) { return a.lo < b.lo; });
-    for (int32_t i = 1; i < count; ++i)
+    for (size_t i = 1; i < outs.size(); ++i)
         if (outs[i].lo < outs[i - 1].hi) return fail(SOBEL4X5_EINVAL, "outputs of two images overlap");
     // no output may overlap any input
     std::vector<Range> ins(count);
@@ -255,6 +270,8 @@ struct sobel4x5_plan_s {
     bool use_graph = true;
     bool aligned = true;
     std::vector<sobel4x5_image> imgs;
+    std::vector<sobel4x5_outputs> outs;   // per image: mag and/or directional planes
+    bool dir = false;                     // some image asks for directional planes
     U8Job *d_jobs = nullptr;
     int4 *d_tiles = nullptr;      // {image, kind | rows << 1, tx, y0} per queue ticket
     int32_t total = 0;            // wave-tiles of the batch
@@ -284,16 +301,19 @@ int plan_setup(sobel4x5_plan_s *p, const U8Shape &shape)
 {
     plan_free_device(p);
     p->shape = shape;
-    const int valid = p->border == SOBEL4X5_BORDER_VALID;
     std::vector<U8Job> jobs(p->count);
     bool aligned = true;
     for (int32_t i = 0; i < p->count; ++i) {
         const sobel4x5_image &m = p->imgs[i];
+        const sobel4x5_outputs &o = p->outs[i];
         int32_t Wo, Ho;
         out_dims(m.width, m.height, p->border, &Wo, &Ho);
-        jobs[i] = make_job(m.src, m.width, m.height, m.src_pitch, Wo, Ho, m.mag, m.mag_pitch, nullptr, 0, 0);
+        jobs[i] = make_job(m.src, m.width, m.height, m.src_pitch, Wo, Ho, o.mag, o.mag_pitch,
+                           o.dir_type ? o.dir : nullptr, o.dir_pitch, o.dir_type);
         u8_tile(jobs[i], shape);
-        aligned = aligned && u8_rows_aligned(jobs[i]);
+        // reflect-101 on an image narrower than 3 columns needs the byte path
+        aligned = aligned && u8_rows_aligned(jobs[i]) &&
+                  !(p->border == SOBEL4X5_BORDER_REFLECT101 && m.width < 3);
     }
     p->aligned = aligned;
     std::vector<int4> tiles, tail;
@@ -317,7 +337,7 @@ int plan_setup(sobel4x5_plan_s *p, const U8Shape &shape)
         plan_free_device(p);
         return hip_fail(e, "uploading plan tables");
     }
-    p->grid = u8_persistent_grid(shape, valid, p->aligned);
+    p->grid = u8_persistent_grid(shape, p->border, p->aligned, p->dir);
     if (p->grid <= 0) {
         plan_free_device(p);
         return fail(SOBEL4X5_EHIP, "could not query occupancy");
@@ -329,8 +349,8 @@ int plan_setup(sobel4x5_plan_s *p, const U8Shape &shape)
 
 int plan_direct_launch(sobel4x5_plan_s *p, hipStream_t st)
 {
-    hipError_t e = launch_u8_batched(p->d_jobs, p->d_tiles, p->total, p->d_queue,
-                                     p->border == SOBEL4X5_BORDER_VALID, p->aligned, p->shape, p->grid, st);
+    hipError_t e = launch_u8_batched(p->d_jobs, p->d_tiles, p->total, p->d_queue, p->border, p->aligned, p->dir,
+                                     p->shape, p->grid, st);
     return e == hipSuccess ? ok() : hip_fail(e, "batched launch");
 }
 
@@ -361,23 +381,43 @@ int plan_capture(sobel4x5_plan_s *p)
     return rc;
 }
 
-// Order-independent 64-bit fingerprint of every image's output, used by the
+// Every output plane of image i: (device pointer, pitch, row bytes, rows).
+struct Plane {
+    void *p;
+    int64_t pitch, row_bytes, rows;
+};
+
+std::vector<Plane> image_planes(const sobel4x5_plan_s *p, int32_t i)
+{
+    const sobel4x5_image &m = p->imgs[i];
+    const sobel4x5_outputs &o = p->outs[i];
+    int32_t Wo, Ho;
+    out_dims(m.width, m.height, p->border, &Wo, &Ho);
+    std::vector<Plane> v;
+    if (o.mag) v.push_back({o.mag, o.mag_pitch, Wo, Ho});
+    if (o.dir_type != SOBEL4X5_DIR_NONE) {
+        const int64_t es = o.dir_type == SOBEL4X5_DIR_S16 ? 2 : 4;
+        for (int k = 0; k < 4; ++k) v.push_back({o.dir[k], o.dir_pitch, Wo * es, Ho});
+    }
+    return v;
+}
+
+// Order-independent 64-bit fingerprint of every output plane, used by the
 // autotuner to check that a candidate shape reproduces the reference bytes.
 int batch_fingerprint(const sobel4x5_plan_s *p, std::vector<uint64_t> &out)
 {
-    out.assign(p->count, 0);
+    out.clear();
     std::vector<uint8_t> host;
-    for (int32_t i = 0; i < p->count; ++i) {
-        const sobel4x5_image &m = p->imgs[i];
-        int32_t Wo, Ho;
-        out_dims(m.width, m.height, p->border, &Wo, &Ho);
-        host.resize((size_t)Wo * Ho);
-        hipError_t e = hipMemcpy2D(host.data(), Wo, m.mag, m.mag_pitch, Wo, Ho, hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return hip_fail(e, "reading outputs for verification");
-        uint64_t h = 1469598103934665603ull;
-        for (uint8_t b : host) h = (h ^ b) * 1099511628211ull;
-        out[i] = h;
-    }
+    for (int32_t i = 0; i < p->count; ++i)
+        for (const Plane &pl : image_planes(p, i)) {
+            host.resize((size_t)(pl.row_bytes * pl.rows));
+            hipError_t e = hipMemcpy2D(host.data(), pl.row_bytes, pl.p, pl.pitch, pl.row_bytes, pl.rows,
+                                       hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_fail(e, "reading outputs for verification");
+            uint64_t h = 1469598103934665603ull;
+            for (uint8_t b : host) h = (h ^ b) * 1099511628211ull;
+            out.push_back(h);
+        }
     return ok();
 }
 
@@ -429,8 +469,8 @@ std::string tune_key(const sobel4x5_plan_s *p)
         px += (int64_t)m.width * m.height;
     }
     char buf[256];
-    std::snprintf(buf, sizeof buf, "v%d|%s|b%d|n%d|px%lld|h%016llx", SOBEL4X5_VERSION, prop.gcnArchName,
-                  p->border, p->count, (long long)px, (unsigned long long)h);
+    std::snprintf(buf, sizeof buf, "v%d|%s|b%d|d%d|n%d|px%lld|h%016llx", SOBEL4X5_VERSION, prop.gcnArchName,
+                  p->border, (int)p->dir, p->count, (long long)px, (unsigned long long)h);
     std::string key = buf;
     for (char &c : key)
         if (c == ' ' || c == '\n') c = '_';
@@ -465,13 +505,13 @@ void tune_store(const std::string &key, const U8Shape &s)
     std::fclose(f);
 }
 
-// Shape of a batched plan without autotuning: 16 pixels per lane, 32-row
-// tiles; SOBEL4X5_BATCH_PPL (8 or 16) and SOBEL4X5_BATCH_TH (4..256)
-// override it.
-U8Shape batch_default_shape(const std::vector<sobel4x5_image> &imgs)
+// Shape of a batched plan without autotuning: 16 pixels per lane (8 with
+// directional planes, whose stores keep more values live), 32-row tiles;
+// SOBEL4X5_BATCH_PPL (8 or 16) and SOBEL4X5_BATCH_TH (4..256) override it.
+U8Shape batch_default_shape(const std::vector<sobel4x5_image> &imgs, bool dir)
 {
     (void)imgs;
-    U8Shape s{16, 32, 4};
+    U8Shape s{dir ? 8 : 16, 32, 4};
     const int ppl = env_int("SOBEL4X5_BATCH_PPL", 0);
     if (ppl == 8 || ppl == 16) s.ppl = ppl;
     const int th = env_int("SOBEL4X5_BATCH_TH", 0);
@@ -486,7 +526,7 @@ int plan_autotune(sobel4x5_plan_s *p)
     if (tune_lookup(key, cached)) return plan_setup(p, cached);
 
     // reference bytes with the default shape
-    const U8Shape ref = batch_default_shape(p->imgs);
+    const U8Shape ref = batch_default_shape(p->imgs, p->dir);
     if (int rc = plan_setup(p, ref)) return rc;
     if (int rc = plan_direct_launch(p, nullptr)) return rc;
     if (hipError_t e = hipDeviceSynchronize(); e != hipSuccess) return hip_fail(e, "autotune reference run");
@@ -503,11 +543,8 @@ int plan_autotune(sobel4x5_plan_s *p)
             if (c.ppl == ref.ppl && c.th == ref.th) continue;
             if (plan_setup(p, c) != SOBEL4X5_OK) continue;
             // clear outputs so that a candidate that skips pixels cannot pass
-            for (const auto &m : p->imgs) {
-                int32_t Wo, Ho;
-                out_dims(m.width, m.height, p->border, &Wo, &Ho);
-                hipMemset2D(m.mag, m.mag_pitch, 0xA5, Wo, Ho);
-            }
+            for (int32_t i = 0; i < p->count; ++i)
+                for (const Plane &pl : image_planes(p, i)) hipMemset2D(pl.p, pl.pitch, 0xA5, pl.row_bytes, pl.rows);
             if (plan_direct_launch(p, nullptr) != SOBEL4X5_OK) continue;
             if (hipDeviceSynchronize() != hipSuccess) return fail(SOBEL4X5_EHIP, "autotune candidate run failed");
             if (batch_fingerprint(p, got) != SOBEL4X5_OK || got != want) continue;   // never trust a mismatch
@@ -534,9 +571,12 @@ PlanCache &plan_cache()
     return *c;
 }
 
-std::string batch_key(const sobel4x5_image *imgs, int32_t count, int32_t border, int device)
+std::string batch_key(const sobel4x5_image *imgs, const sobel4x5_outputs *outs, int32_t count, int32_t border,
+                      int device)
 {
     std::string k(reinterpret_cast<const char *>(imgs), sizeof(sobel4x5_image) * (size_t)count);
+    if (outs) k.append(reinterpret_cast<const char *>(outs), sizeof(sobel4x5_outputs) * (size_t)count);
+    k.push_back(outs ? 'o' : 'm');
     k.append(reinterpret_cast<const char *>(&border), sizeof border);
     k.append(reinterpret_cast<const char *>(&device), sizeof device);
     return k;
@@ -640,7 +680,7 @@ int sobel4x5_u8(const uint8_t *src, int32_t width, int32_t height, int64_t src_p
                        out->dir_type ? out->dir : nullptr, out->dir_pitch, out->dir_type);
     const U8Shape s = default_shape(Wo, Ho, out->dir_type);
     u8_tile(j, s);
-    hipError_t e = launch_u8_single(j, border == SOBEL4X5_BORDER_VALID, s, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_u8_single(j, border, s, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_u8 launch");
 }
 
@@ -666,21 +706,27 @@ int sobel4x5_u8_op(const uint8_t *src, int32_t width, int32_t height, int64_t sr
                        out->dir_type ? dirs : nullptr, out->dir_pitch, out->dir_type);
     const U8Shape s = default_shape(Wo, Ho, out->dir_type);
     u8_tile(j, s);
-    hipError_t e = launch_u8_2dir(j, op, border == SOBEL4X5_BORDER_VALID, s, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_u8_2dir(j, op, border, s, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_u8_op launch");
 }
 
 int sobel4x5_validate_batch(const sobel4x5_image *imgs, int32_t count, int32_t border)
 {
-    return validate_batch(imgs, count, border);
+    return validate_batch(imgs, nullptr, count, border);
 }
 
-int sobel4x5_plan_create(const sobel4x5_image *imgs, int32_t count, int32_t border, uint32_t flags,
-                         sobel4x5_plan *out)
+int sobel4x5_validate_batch_ex(const sobel4x5_image *imgs, const sobel4x5_outputs *outs, int32_t count,
+                               int32_t border)
+{
+    return validate_batch(imgs, outs, count, border);
+}
+
+int sobel4x5_plan_create_ex(const sobel4x5_image *imgs, const sobel4x5_outputs *outs, int32_t count, int32_t border,
+                            uint32_t flags, sobel4x5_plan *out)
 {
     if (!out) return fail(SOBEL4X5_EINVAL, "out is NULL");
     *out = nullptr;
-    if (int rc = validate_batch(imgs, count, border)) return rc;
+    if (int rc = validate_batch(imgs, outs, count, border)) return rc;
     if (flags & ~(SOBEL4X5_PLAN_AUTOTUNE | SOBEL4X5_PLAN_NO_GRAPH))
         return fail(SOBEL4X5_EINVAL, "unknown plan flags 0x%x", flags);
     auto *p = new (std::nothrow) sobel4x5_plan_s();
@@ -689,8 +735,13 @@ int sobel4x5_plan_create(const sobel4x5_image *imgs, int32_t count, int32_t bord
     p->border = border;
     p->use_graph = !(flags & SOBEL4X5_PLAN_NO_GRAPH);
     p->imgs.assign(imgs, imgs + count);
+    p->outs.resize(count);
+    for (int32_t i = 0; i < count; ++i) {
+        p->outs[i] = batch_outputs(imgs, outs, i);
+        p->dir = p->dir || p->outs[i].dir_type != SOBEL4X5_DIR_NONE;
+    }
     hipGetDevice(&p->device);
-    int rc = (flags & SOBEL4X5_PLAN_AUTOTUNE) ? plan_autotune(p) : plan_setup(p, batch_default_shape(p->imgs));
+    int rc = (flags & SOBEL4X5_PLAN_AUTOTUNE) ? plan_autotune(p) : plan_setup(p, batch_default_shape(p->imgs, p->dir));
     if (rc == SOBEL4X5_OK && p->use_graph) rc = plan_capture(p);
     if (rc != SOBEL4X5_OK) {
         plan_free_device(p);
@@ -700,6 +751,12 @@ int sobel4x5_plan_create(const sobel4x5_image *imgs, int32_t count, int32_t bord
     }
     *out = p;
     return ok();
+}
+
+int sobel4x5_plan_create(const sobel4x5_image *imgs, int32_t count, int32_t border, uint32_t flags,
+                         sobel4x5_plan *out)
+{
+    return sobel4x5_plan_create_ex(imgs, nullptr, count, border, flags, out);
 }
 
 int sobel4x5_plan_launch(sobel4x5_plan plan, void *stream)
@@ -733,12 +790,13 @@ int sobel4x5_plan_destroy(sobel4x5_plan plan)
     return ok();
 }
 
-int sobel4x5_batched(const sobel4x5_image *imgs, int32_t count, int32_t border, void *stream)
+int sobel4x5_batched_ex(const sobel4x5_image *imgs, const sobel4x5_outputs *outs, int32_t count, int32_t border,
+                        void *stream)
 {
-    if (int rc = validate_batch(imgs, count, border)) return rc;
+    if (int rc = validate_batch(imgs, outs, count, border)) return rc;
     int dev = 0;
     hipGetDevice(&dev);
-    const std::string key = batch_key(imgs, count, border, dev);
+    const std::string key = batch_key(imgs, outs, count, border, dev);
     PlanCache &c = plan_cache();
     sobel4x5_plan plan = nullptr;
     {
@@ -753,7 +811,7 @@ int sobel4x5_batched(const sobel4x5_image *imgs, int32_t count, int32_t border, 
             }
     }
     if (!plan) {
-        if (int rc = sobel4x5_plan_create(imgs, count, border, 0, &plan)) return rc;
+        if (int rc = sobel4x5_plan_create_ex(imgs, outs, count, border, 0, &plan)) return rc;
         std::lock_guard<std::mutex> lk(c.mu);
         c.lru.emplace_back(key, plan);
         if (c.lru.size() > 8) {
@@ -766,12 +824,19 @@ int sobel4x5_batched(const sobel4x5_image *imgs, int32_t count, int32_t border, 
     return sobel4x5_plan_launch(plan, stream);
 }
 
+int sobel4x5_batched(const sobel4x5_image *imgs, int32_t count, int32_t border, void *stream)
+{
+    return sobel4x5_batched_ex(imgs, nullptr, count, border, stream);
+}
+
 int sobel4x5_validate_f32(const float *src, int32_t batch, int32_t width, int32_t height, int64_t src_pitch,
                           int64_t src_bstride, int32_t border, const float *out, int64_t out_pitch,
                           int64_t out_bstride)
 {
     int32_t Wo, Ho;
     if (int rc = out_dims(width, height, border, &Wo, &Ho)) return rc;
+    if (border != SOBEL4X5_BORDER_REPLICATE && border != SOBEL4X5_BORDER_VALID)
+        return fail(SOBEL4X5_EUNSUPPORTED, "the fp32 path serves the REPLICATE and VALID borders only");
     if (batch < 0) return fail(SOBEL4X5_EINVAL, "batch must be >= 0");
     Range rs, ro;
     if (int rc = check_f32_buf("src", src, batch, width, height, src_pitch, src_bstride, &rs)) return rc;
@@ -809,6 +874,8 @@ int sobel4x5_f32_bwd(const float *src, int64_t src_pitch, int64_t src_bstride, c
 {
     int32_t Wo, Ho;
     if (int rc = out_dims(width, height, border, &Wo, &Ho)) return rc;
+    if (border != SOBEL4X5_BORDER_REPLICATE && border != SOBEL4X5_BORDER_VALID)
+        return fail(SOBEL4X5_EUNSUPPORTED, "the fp32 path serves the REPLICATE and VALID borders only");
     if (batch < 0) return fail(SOBEL4X5_EINVAL, "batch must be >= 0");
     Range rs, rg, rd;
     if (int rc = check_f32_buf("src", src, batch, width, height, src_pitch, src_bstride, &rs)) return rc;
@@ -912,6 +979,7 @@ int sobel4x5_u8_weighted(const uint8_t *src, int32_t width, int32_t height, int6
     j.Wo = Wo;
     j.Ho = Ho;
     j.off = border == SOBEL4X5_BORDER_VALID ? 2 : 0;
+    j.bmode = border == SOBEL4X5_BORDER_ZERO ? 1 : (border == SOBEL4X5_BORDER_REFLECT101 ? 2 : 0);
     j.dir_type = out->dir_type;
     // upper-half taps (0, 0..4), (1, 0..4), (2, 0), (2, 1)
     for (int k = 0; k < 4; ++k)
@@ -972,8 +1040,6 @@ int sobel4x5_pipe_run(sobel4x5_pipe p, const sobel4x5_image *imgs, int32_t count
 {
     if (!p) return fail(SOBEL4X5_EINVAL, "pipe is NULL");
     if (count < 0 || (count > 0 && !imgs)) return fail(SOBEL4X5_EINVAL, "bad image array");
-    if (border != SOBEL4X5_BORDER_REPLICATE && border != SOBEL4X5_BORDER_VALID)
-        return fail(SOBEL4X5_EINVAL, "border must be 0 or 1, got %d", border);
     for (int32_t i = 0; i < count; ++i) {
         const sobel4x5_image &m = imgs[i];
         int32_t Wo, Ho;
@@ -986,7 +1052,6 @@ int sobel4x5_pipe_run(sobel4x5_pipe p, const sobel4x5_image *imgs, int32_t count
         if (int rc = check_pitch("mag", m.mag_pitch, Wo, Ho)) return rc;
     }
     const int depth = (int)p->slots.size();
-    const bool valid = border == SOBEL4X5_BORDER_VALID;
     auto drain = [&](PipeSlot &sl) -> hipError_t {
         if (sl.pending < 0) return hipSuccess;
         hipError_t e = hipStreamSynchronize(sl.st);
@@ -1014,7 +1079,7 @@ int sobel4x5_pipe_run(sobel4x5_pipe p, const sobel4x5_image *imgs, int32_t count
         U8Job j = make_job(sl.d_src, m.width, m.height, sl.pitch, Wo, Ho, sl.d_mag, sl.pitch, nullptr, 0, 0);
         const U8Shape shape = default_shape(Wo, Ho, SOBEL4X5_DIR_NONE);
         u8_tile(j, shape);
-        if ((e = launch_u8_single(j, valid, shape, sl.st)) != hipSuccess) return hip_fail(e, "pipeline launch");
+        if ((e = launch_u8_single(j, border, shape, sl.st)) != hipSuccess) return hip_fail(e, "pipeline launch");
         sl.staged_out = !is_pinned(m.mag);
         e = hipMemcpy2DAsync(sl.staged_out ? sl.h_mag : m.mag, sl.staged_out ? sl.pitch : m.mag_pitch, sl.d_mag,
                              sl.pitch, Wo, Ho, hipMemcpyDeviceToHost, sl.st);

@@ -1,0 +1,160 @@
+// Batched uint8 four-directional kernel: many images of uneven sizes in one
+// persistent launch of the sweep in u8_sweep.hpp, for every border rule,
+// with or without directional planes.
+
+#include "u8_sweep.hpp"
+
+namespace s4x5 {
+namespace {
+
+// Geometry of one wave-tile of the batched kernel, ti = {image, kind | rows << 1,
+// tx, y0} (built on the host by batched_tiles):
+//   kind 0: four tiles side by side, tile columns tx .. tx+3 (a complete
+//           strip), output rows [y0, y0 + rows): every group walks the same
+//           rows and each load instruction covers one contiguous row segment;
+//   kind 1: four tiles of th rows stacked in tile column tx, starting at
+//           row y0, for the columns an image has beyond its last complete
+//           strip.
+__device__ __forceinline__ Sweep batch_geometry(const U8Job &J, const int4 &ti, int ppl, int th)
+{
+    const int tw = 16 * ppl;
+    const int grp = (threadIdx.x >> 4) & 3;
+    const int lane16 = threadIdx.x & 15;
+    Sweep g;
+    if ((ti.y & 1) == 0) {
+        const int tx = ti.z + grp;
+        g.xo = tx * tw + lane16 * ppl;
+        g.yo0 = ti.w;
+        g.nrow = min(ti.y >> 1, J.Ho - g.yo0);
+        g.niter = g.nrow;
+        g.fix_right = (ti.z + 4) * tw + 4 > J.W;
+        g.fix_left = ti.z == 0;
+    } else {
+        g.xo = ti.z * tw + lane16 * ppl;
+        g.yo0 = ti.w + grp * th;
+        g.nrow = g.yo0 < J.Ho ? min(th, J.Ho - g.yo0) : 0;
+        g.niter = max(max(__builtin_amdgcn_readlane(g.nrow, 0), __builtin_amdgcn_readlane(g.nrow, 16)),
+                      max(__builtin_amdgcn_readlane(g.nrow, 32), __builtin_amdgcn_readlane(g.nrow, 48)));
+        g.fix_right = (ti.z + 1) * tw + 4 > J.W;
+        g.fix_left = ti.z == 0;
+    }
+    return g;
+}
+
+// Persistent work-queue kernel: every wave takes the next wave-tile of the
+// whole batch from queue[0] until none are left, then counts itself out in
+// queue[1]; the last wave out resets both words for the next launch.  A
+// ticket indexes the host-built tile table, so finding a tile is one load.
+// DIR: images whose job asks for them also get their directional planes.
+template <int PPL, int OFF, bool ALIGNED, bool DIR, int BM>
+__global__ __launch_bounds__(64 * kWaves) void k_u8_batched(const U8Job *__restrict__ jobs,
+                                                            const int4 *__restrict__ tiles, int32_t total,
+                                                            uint32_t *queue, int TH)
+{
+    constexpr int TW = 16 * PPL;
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        u32 tv = 0;
+        if (lane == 0) tv = atomicAdd(&queue[0], 1u);
+        const int t = __builtin_amdgcn_readfirstlane((int)tv);
+        if (t >= total) break;
+        const int4 ti = tiles[t];
+        const U8Job J = jobs[ti.x];
+        Sweep g = batch_geometry(J, ti, PPL, TH);
+        g.fix_left = g.fix_left && OFF == 0;
+        if (g.niter <= 0) continue;
+        // fast: every group has its full rows, every lane's block and output
+        // inside the image
+        bool fast;
+        if ((ti.y & 1) == 0) {
+            fast = ALIGNED && (ti.z + 4) * TW <= J.Wo;
+        } else {
+            const bool full = __builtin_amdgcn_readlane(g.nrow, 0) == TH && __builtin_amdgcn_readlane(g.nrow, 16) == TH &&
+                              __builtin_amdgcn_readlane(g.nrow, 32) == TH && __builtin_amdgcn_readlane(g.nrow, 48) == TH;
+            fast = ALIGNED && full && (ti.z + 1) * TW <= J.Wo;
+        }
+        if (fast && !g.fix_right && !g.fix_left)
+            sweep<PPL, OFF, ALIGNED, DIR, true, false, kOp4x5, BM>(J, g);
+        else if (fast)
+            sweep<PPL, OFF, ALIGNED, DIR, true, true, kOp4x5, BM>(J, g);
+        else
+            sweep<PPL, OFF, ALIGNED, DIR, false, false, kOp4x5, BM>(J, g);
+    }
+    if (lane == 0) {
+        __threadfence();
+        const u32 nwaves = gridDim.x * kWaves;
+        if (atomicAdd(&queue[1], 1u) == nwaves - 1) {
+            queue[0] = 0;
+            queue[1] = 0;
+            __threadfence();
+        }
+    }
+}
+
+template <int PPL, int OFF, int BM>
+const void *batched_fn(bool aligned, bool dir)
+{
+    if (dir)
+        return aligned ? reinterpret_cast<const void *>(&k_u8_batched<PPL, OFF, true, true, BM>)
+                       : reinterpret_cast<const void *>(&k_u8_batched<PPL, OFF, false, true, BM>);
+    return aligned ? reinterpret_cast<const void *>(&k_u8_batched<PPL, OFF, true, false, BM>)
+                   : reinterpret_cast<const void *>(&k_u8_batched<PPL, OFF, false, false, BM>);
+}
+
+template <int PPL>
+const void *pick_ppl(int border, bool aligned, bool dir)
+{
+    switch (border) {
+    case 1: return batched_fn<PPL, 2, kBmRep>(aligned, dir);
+    case 2: return batched_fn<PPL, 0, kBmZero>(aligned, dir);
+    case 3: return batched_fn<PPL, 0, kBmRefl>(aligned, dir);
+    default: return batched_fn<PPL, 0, kBmRep>(aligned, dir);
+    }
+}
+
+// border: the public SOBEL4X5_BORDER_* code
+const void *pick_batched(int ppl, int border, bool aligned, bool dir)
+{
+    return ppl == 16 ? pick_ppl<16>(border, aligned, dir) : pick_ppl<8>(border, aligned, dir);
+}
+
+}  // namespace
+
+void batched_tiles(const U8Job &j, int32_t img, int th, std::vector<int4> &first, std::vector<int4> &last)
+{
+    // side-by-side strips: the top three quarters of the rows (rounded down
+    // to whole tall chunks of 4 th rows) in tall chunks, the rest in chunks
+    // of th rows, queued after every tall chunk of the batch
+    const int strips = j.ntx / 4, tall = 4 * th;
+    const int htall = (j.Ho - j.Ho / 4) / tall * tall;
+    for (int y = 0; y < htall; y += tall)
+        for (int s = 0; s < strips; ++s) first.push_back(make_int4(img, tall << 1, 4 * s, y));
+    for (int y = htall; y < j.Ho; y += th)
+        for (int s = 0; s < strips; ++s) last.push_back(make_int4(img, th << 1, 4 * s, y));
+    // remaining tile columns: four row blocks stacked
+    for (int tx = 4 * strips; tx < j.ntx; ++tx)
+        for (int y = 0; y < j.Ho; y += 4 * th) first.push_back(make_int4(img, 1, tx, y));
+}
+
+hipError_t launch_u8_batched(const U8Job *jobs, const int4 *tiles, int32_t total, uint32_t *queue, int border,
+                             bool aligned, bool dir, const U8Shape &s, int grid, hipStream_t st)
+{
+    const void *fn = pick_batched(s.ppl, border, aligned, dir);
+    int th = s.th;
+    void *args[] = {(void *)&jobs, (void *)&tiles, (void *)&total, (void *)&queue, (void *)&th};
+    return hipLaunchKernel(fn, dim3(grid), dim3(64 * kWaves), args, 0, st);
+}
+
+int u8_persistent_grid(const U8Shape &s, int border, bool aligned, bool dir)
+{
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick_batched(s.ppl, border, aligned, dir),
+                                                     64 * kWaves, 0) != hipSuccess)
+        return 0;
+    if (per_cu < 1) per_cu = 1;
+    return ncu * per_cu;
+}
+
+}  // namespace s4x5

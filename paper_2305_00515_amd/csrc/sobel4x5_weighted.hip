@@ -24,6 +24,7 @@
 // a wave covers 256 columns.
 
 #include "internal.hpp"
+#include "load_columns.hpp"
 
 #include <algorithm>
 #include <mutex>
@@ -55,7 +56,8 @@ using PhW = std::integral_constant<int, P>;
 __device__ __forceinline__ constexpr int tap_i(int t) { return t < 5 ? 0 : (t < 10 ? 1 : 2); }
 __device__ __forceinline__ constexpr int tap_j(int t) { return t < 10 ? t % 5 : t - 10; }
 
-template <int OFF, int DT>
+// BM: how pixels outside the image read (0 nearest, 1 zero, 2 reflect-101).
+template <int OFF, int DT, int BM>
 __global__ __launch_bounds__(64 * kWavesW) void k_u8_weighted(WJob J, int nstrip, int nchunk)
 {
     const int wave = blockIdx.x * kWavesW + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -65,16 +67,28 @@ __global__ __launch_bounds__(64 * kWavesW) void k_u8_weighted(WJob J, int nstrip
     if (y1 <= y0) return;
     const int lane = threadIdx.x & 63;
     const int xo = s * kColsW + lane * kPplW;          // first output column of the lane
-    int col[kPplW + 4];                                 // clamped input columns of the window
+    int col[kPplW + 4];                                 // input columns of the window, mapped inside
+    u32 colin = 0;                                      // zero border: bit j = column j lies inside
 #pragma unroll
-    for (int j = 0; j < kPplW + 4; ++j) col[j] = clampi(xo + OFF - 2 + j, 0, J.W - 1);
+    for (int j = 0; j < kPplW + 4; ++j) {
+        const int x = xo + OFF - 2 + j;
+        col[j] = BM == 2 ? reflect101(x, J.W) : clampi(x, 0, J.W - 1);
+        colin |= (x >= 0 && x < J.W) ? (1u << j) : 0u;
+    }
     const GMEM uint8_t *src = (const GMEM uint8_t *)J.src;
     const int r0 = y0 + OFF - 2;                       // input row of step 0
     const int T = y1 - y0 + 4;
     auto ldrow = [&](int t, uint8_t (&v)[kPplW + 4]) {
-        const GMEM uint8_t *row = src + (int64_t)clampi(r0 + min(t, T - 1), 0, J.H - 1) * J.src_pitch;
+        const int r = r0 + min(t, T - 1);
+        const int rr = BM == 2 ? reflect101(r, J.H) : clampi(r, 0, J.H - 1);
+        const GMEM uint8_t *row = src + (int64_t)rr * J.src_pitch;
 #pragma unroll
         for (int j = 0; j < kPplW + 4; ++j) v[j] = row[col[j]];
+        if constexpr (BM == 1) {
+            const bool rin = (unsigned)r <= (unsigned)(J.H - 1);
+#pragma unroll
+            for (int j = 0; j < kPplW + 4; ++j) v[j] = (rin && ((colin >> j) & 1u)) ? v[j] : (uint8_t)0;
+        }
     };
 
     // bytes, so that every pair difference is known to fit 24 bits
@@ -179,10 +193,12 @@ int resident_w(const void *fn)
     return w;
 }
 
-template <int OFF, int DT>
-const void *weighted_fn()
+template <int OFF, int BM>
+const void *weighted_fn(int dir_type)
 {
-    return reinterpret_cast<const void *>(&k_u8_weighted<OFF, DT>);
+    return dir_type == 2 ? reinterpret_cast<const void *>(&k_u8_weighted<OFF, 2, BM>)
+                         : dir_type == 1 ? reinterpret_cast<const void *>(&k_u8_weighted<OFF, 1, BM>)
+                                         : reinterpret_cast<const void *>(&k_u8_weighted<OFF, 0, BM>);
 }
 
 }  // namespace
@@ -190,8 +206,9 @@ const void *weighted_fn()
 hipError_t launch_u8_weighted(const WJob &j, hipStream_t st)
 {
     if (j.Wo <= 0 || j.Ho <= 0) return hipSuccess;
-    const void *fn = j.off ? (j.dir_type == 2 ? weighted_fn<2, 2>() : j.dir_type == 1 ? weighted_fn<2, 1>() : weighted_fn<2, 0>())
-                           : (j.dir_type == 2 ? weighted_fn<0, 2>() : j.dir_type == 1 ? weighted_fn<0, 1>() : weighted_fn<0, 0>());
+    const void *fn = j.off ? weighted_fn<2, 0>(j.dir_type)
+                           : j.bmode == 1 ? weighted_fn<0, 1>(j.dir_type)
+                                          : j.bmode == 2 ? weighted_fn<0, 2>(j.dir_type) : weighted_fn<0, 0>(j.dir_type);
     int nstrip = (j.Wo + kColsW - 1) / kColsW;
     int slots = resident_w(fn);
     if (slots <= 0) slots = 4096;

@@ -6,35 +6,18 @@
 //
 // Offsets: the 3x3 pair has radius 1, so its VALID output is centred on
 // input pixel (y + 1, x + 1); the 5x5 pair, like the four-directional
-// operator, on (y + 2, x + 2).
+// operator, on (y + 2, x + 2).  This file holds the replicate and valid
+// borders; sobel_2dir_u8_border.hip the zero and reflect-101 ones.
 
 #include "u8_sweep.hpp"
 
 namespace s4x5 {
-namespace {
 
-template <int PPL, int OFF, int OPR>
-hipError_t launch_2dir_d(const U8Job &j, const U8Shape &s, hipStream_t st)
+hipError_t launch_u8_2dir(const U8Job &j, int op, int border, const U8Shape &s, hipStream_t st)
 {
-    return j.dir_type ? launch_single_t<PPL, OFF, true, OPR>(j, s, st)
-                      : launch_single_t<PPL, OFF, false, OPR>(j, s, st);
-}
-
-template <int OPR, int VOFF>
-hipError_t launch_2dir_o(const U8Job &j, int border_valid, const U8Shape &s, hipStream_t st)
-{
-    if (s.ppl == 16)
-        return border_valid ? launch_2dir_d<16, VOFF, OPR>(j, s, st) : launch_2dir_d<16, 0, OPR>(j, s, st);
-    return border_valid ? launch_2dir_d<8, VOFF, OPR>(j, s, st) : launch_2dir_d<8, 0, OPR>(j, s, st);
-}
-
-}  // namespace
-
-hipError_t launch_u8_2dir(const U8Job &j, int op, int border_valid, const U8Shape &s, hipStream_t st)
-{
-    if (j.ntx <= 0 || j.Ho <= 0) return hipSuccess;
-    if (op == kOp2x3) return launch_2dir_o<kOp2x3, 1>(j, border_valid, s, st);
-    if (op == kOp2x5) return launch_2dir_o<kOp2x5, 2>(j, border_valid, s, st);
+    if (border == 2 || border == 3) return launch_u8_2dir_zr(j, op, border, s, st);
+    if (op == kOp2x3) return launch_single_border<kOp2x3, 1, kBmRep>(j, border == 1, s, st);
+    if (op == kOp2x5) return launch_single_border<kOp2x5, 2, kBmRep>(j, border == 1, s, st);
     return hipErrorInvalidValue;
 }
 

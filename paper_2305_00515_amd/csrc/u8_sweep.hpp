@@ -81,6 +81,12 @@ __device__ __forceinline__ u32 perm(u32 hi, u32 lo, u32 sel) { return __builtin_
 constexpr u32 kZeroByte = 0x0c;   // v_perm selector that yields 0x00
 constexpr int kPD = 4;            // rows loaded ahead of use
 
+// How pixels outside the image read (VALID uses kBmRep: its outputs never
+// reach outside).
+constexpr int kBmRep = 0;    // the nearest edge pixel
+constexpr int kBmZero = 1;   // 0
+constexpr int kBmRefl = 2;   // reflect-101: mirrored about the edge pixel
+
 // Operators the sweep computes (the values of the public SOBEL4X5_OP_*).
 constexpr int kOp4x5 = 0;   // Eq. (sobel5_1) + Eq. (sobel5_2): four directions, 5x5
 constexpr int kOp2x5 = 1;   // the 0 and 90 deg filters of Eq. (sobel5_1) alone
@@ -279,18 +285,79 @@ __device__ __forceinline__ void load_row(RawRow<PPL> &r, const GMEM uint8_t *row
     r.hw = *reinterpret_cast<const GMEM u32 *>(rowp + hx);
 }
 
+// Window byte b (runtime, 0 .. PPL+5; column xo - 2 + b) and its update.
+template <int PPL>
+__device__ __forceinline__ u32 win_get(const Win<PPL> &w, int b)
+{
+    u32 word = w.Rt;
+    int sh = 8 * (b - PPL - 2);
+    if (b < 2) {
+        word = w.L;
+        sh = 8 * (b + 2);
+    } else if (b < PPL + 2) {
+#pragma unroll
+        for (int m = 0; m < PPL / 4; ++m)
+            if (((b - 2) >> 2) == m) word = w.d[m];
+        sh = 8 * ((b - 2) & 3);
+    }
+    return (word >> sh) & 0xffu;
+}
+
+template <int PPL>
+__device__ __forceinline__ void win_set(Win<PPL> &w, int b, u32 v)
+{
+    auto put = [&](u32 &word, int pos) {
+        const u32 m = 0xffu << (8 * pos);
+        word = (word & ~m) | ((v << (8 * pos)) & m);
+    };
+    if (b < 2) {
+        put(w.L, b + 2);
+    } else if (b < PPL + 2) {
+#pragma unroll
+        for (int m = 0; m < PPL / 4; ++m)
+            if (((b - 2) >> 2) == m) put(w.d[m], (b - 2) & 3);
+    } else {
+        put(w.Rt, b - PPL - 2);
+    }
+}
+
+// Reflect-101 at the right edge, on a lane's window after the halo
+// exchange: columns W and W+1 (the only ones past the edge that an output
+// inside the image reads) take columns W-2 and W-3.  A lane with an output
+// inside the image (xo <= W-1) holds both sources in its window.  Needs
+// W >= 3 (narrower images take the byte path).
+template <int PPL>
+__device__ __forceinline__ void reflect_right(Win<PPL> &w, int xo, int W)
+{
+    const int nv = W - xo;
+    if (nv >= 1 && nv <= PPL + 3) {
+        win_set<PPL>(w, nv + 2, win_get<PPL>(w, nv));
+        if (nv + 3 <= PPL + 5) win_set<PPL>(w, nv + 3, win_get<PPL>(w, nv - 1));
+    }
+}
+
+// v_perm selector that fills the left-halo dword of the lane at column 0
+// (bytes 2, 3 = columns -2, -1) from its first own dword: replicate puts
+// column 0 everywhere, zero puts 0, reflect-101 puts columns 2 and 1.
+template <int BM>
+constexpr u32 left_sel()
+{
+    return BM == kBmRep ? 0u : (BM == kBmZero ? 0x0c0c0c0cu : 0x01020c0cu);
+}
+
 // Turn a loaded row into the lane's window: border fix-ups, then DPP halo.
-template <int PPL, int OFF>
+template <int PPL, int OFF, int BM>
 __device__ __forceinline__ Win<PPL> finish_row(RawRow<PPL> &r, int lane16, int xo, int W,
                                                bool fix_right, bool fix_left)
 {
     constexpr int ND = PPL / 4;
     if (fix_right) {
         // own block: bytes at columns >= W take the value of column W-1
+        // (zero border: 0; reflect-101 corrects columns W, W+1 below)
         const int nv = W - xo;
         if (nv < PPL) {
             const int lb = nv >= 1 ? nv - 1 : ((W - 1) & (PPL - 1));
-            const u32 fill = byte_of<PPL>(r.d, lb) * 0x01010101u;
+            const u32 fill = BM == kBmZero ? 0u : byte_of<PPL>(r.d, lb) * 0x01010101u;
 #pragma unroll
             for (int m = 0; m < ND; ++m) r.d[m] = keep_bytes(r.d[m], nv - 4 * m, fill);
         }
@@ -298,11 +365,16 @@ __device__ __forceinline__ Win<PPL> finish_row(RawRow<PPL> &r, int lane16, int x
         const int nh = W - (xo + PPL);
         if (lane16 == 15 && nh < 4) {
             const int lb = nh >= 1 ? nh - 1 : ((W - 1) & 3);
-            const u32 fill = ((r.hw >> (8 * lb)) & 0xffu) * 0x01010101u;
+            const u32 fill = BM == kBmZero ? 0u : ((r.hw >> (8 * lb)) & 0xffu) * 0x01010101u;
             r.hw = keep_bytes(r.hw, nh, fill);
         }
     }
-    if (OFF == 0 && fix_left && lane16 == 0 && xo == 0) r.hw = (r.d[0] & 0xffu) * 0x01010101u;
+    if (OFF == 0 && fix_left && lane16 == 0 && xo == 0) {
+        if constexpr (BM == kBmRep)
+            r.hw = (r.d[0] & 0xffu) * 0x01010101u;
+        else
+            r.hw = perm(r.d[0], r.d[0], left_sel<BM>());
+    }
     Win<PPL> w;
 #pragma unroll
     for (int m = 0; m < ND; ++m) w.d[m] = r.d[m];
@@ -310,20 +382,28 @@ __device__ __forceinline__ Win<PPL> finish_row(RawRow<PPL> &r, int lane16, int x
     w.L = (u32)__builtin_amdgcn_update_dpp((int)r.hw, (int)r.d[ND - 1], 0x111, 0xf, 0xf, false);
     // row_shl:1 -> value of lane+1; lane 15 keeps `old`
     w.Rt = (u32)__builtin_amdgcn_update_dpp((int)r.hw, (int)r.d[0], 0x101, 0xf, 0xf, false);
+    if constexpr (BM == kBmRefl)
+        if (fix_right) reflect_right<PPL>(w, xo, W);
     return w;
 }
 
-// Replicate fix-ups of the group halo dwords for a fast wave at the image's
+// Border fix-ups of the group halo dwords for a fast wave at the image's
 // left / right edge (its lanes' own blocks all lie inside the row): loop-
-// invariant per-lane masks, so the fix-up is two v_perm + two v_bfi per row
-// and no branch.  mask bits set = keep the loaded byte.
+// invariant per-lane masks and selectors, so the fix-up is two v_perm + two
+// v_bfi per row and no branch.  mask bits set = keep the loaded byte.
 struct EdgeFix {
-    u32 keep_l;   // lane 0 at column 0 (replicate border): 0, else all ones
+    u32 keep_l;   // lane 0 at column 0 (OFF == 0): 0, else all ones
     u32 keep_r;   // lane 15 whose halo reaches column W: bytes < W - (xo + ppl), else all ones
-    u32 sel_r;    // v_perm selector replicating the byte of column W-1 from (hw, last own dword)
+    u32 sel_r;    // v_perm selector of the replacement bytes from (hw, last own dword)
 };
 
-template <int PPL, int OFF>
+// sel_r by border rule, for nh = W - (xo + ppl) valid halo bytes (0..3):
+//   replicate: the byte of column W-1 everywhere;
+//   zero:      0;
+//   reflect-101: halo byte k (column W + k - nh, k < 2 are the only ones
+//   read) takes column W - 2 - (k - nh), which is byte 2 + 2nh - k of the
+//   pair (last own dword = bytes 0..3, hw = bytes 4..7).
+template <int PPL, int OFF, int BM>
 __device__ __forceinline__ EdgeFix edge_fix(int lane16, int xo, int W, bool at_left, bool at_right)
 {
     EdgeFix e;
@@ -331,27 +411,49 @@ __device__ __forceinline__ EdgeFix edge_fix(int lane16, int xo, int W, bool at_l
     const int nh = W - (xo + PPL);   // valid bytes of the right halo dword (>= 0 here)
     const bool r = at_right && lane16 == 15 && nh < 4;
     e.keep_r = r ? ((1u << (8 * nh)) - 1u) : ~0u;
-    e.sel_r = (nh >= 1 ? (u32)(4 + nh - 1) : 3u) * 0x01010101u;
+    if constexpr (BM == kBmRep) {
+        e.sel_r = (nh >= 1 ? (u32)(4 + nh - 1) : 3u) * 0x01010101u;
+    } else if constexpr (BM == kBmZero) {
+        e.sel_r = 0x0c0c0c0cu;
+    } else {
+        u32 sel = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const u32 b = (k >= nh && k <= 1 && nh >= 0) ? (u32)(2 + 2 * nh - k) : kZeroByte;
+            sel |= b << (8 * k);
+        }
+        e.sel_r = sel;
+    }
     return e;
 }
 
-template <int PPL>
+template <int PPL, int BM>
 __device__ __forceinline__ void apply_edge(RawRow<PPL> &r, const EdgeFix &e)
 {
     constexpr int ND = PPL / 4;
-    const u32 fr = perm(r.hw, r.d[ND - 1], e.sel_r);   // column W-1, four times
-    const u32 fl = perm(r.d[0], r.d[0], 0u);            // column 0, four times
+    const u32 fr = perm(r.hw, r.d[ND - 1], e.sel_r);          // right replacement bytes
+    const u32 fl = perm(r.d[0], r.d[0], left_sel<BM>());       // left replacement bytes
     r.hw = (r.hw & e.keep_r) | (fr & ~e.keep_r);
     r.hw = (r.hw & e.keep_l) | (fl & ~e.keep_l);
 }
 
-// Slow path for rows that are not 16-byte aligned: every window byte is read
-// on its own at its clamped column.
-template <int PPL>
-__device__ __forceinline__ Win<PPL> load_row_bytes(const GMEM uint8_t *rowp, int xo, int W)
+// Slow path for rows that are not 16-byte aligned (and for reflect-101 on
+// images narrower than 3): every window byte is read on its own at the
+// column the border rule maps it to.  row_in: the row lies inside the image
+// (zero border: otherwise every byte reads 0).
+template <int PPL, int BM>
+__device__ __forceinline__ Win<PPL> load_row_bytes(const GMEM uint8_t *rowp, int xo, int W, bool row_in)
 {
     Win<PPL> w;
-    auto px = [&](int x) -> u32 { return rowp[x < 0 ? 0 : (x >= W ? W - 1 : x)]; };
+    auto px = [&](int x) -> u32 {
+        if constexpr (BM == kBmRefl) {
+            return rowp[reflect101(x, W)];
+        } else {
+            const u32 v = rowp[x < 0 ? 0 : (x >= W ? W - 1 : x)];
+            if constexpr (BM == kBmZero) return (row_in && x >= 0 && x < W) ? v : 0u;
+            return v;
+        }
+    };
     w.L = (px(xo - 2) << 16) | (px(xo - 1) << 24);
 #pragma unroll
     for (int m = 0; m < PPL / 4; ++m) {
@@ -486,7 +588,7 @@ struct Sweep {
 // niter rows, every lane's block and outputs inside the image, 16-byte
 // aligned input rows (EDGE: with the group-halo fix-ups of an image edge):
 // the loop body has no branches, so the compiler can schedule across steps.
-template <int PPL, int OFF, bool ALIGNED, bool DIR, bool FAST, bool EDGE, int OPR>
+template <int PPL, int OFF, bool ALIGNED, bool DIR, bool FAST, bool EDGE, int OPR, int BM>
 __device__ void sweep(const U8Job &J, const Sweep &g)
 {
     static_assert(!EDGE || FAST, "edge fix-ups by mask exist for fast waves only");
@@ -503,11 +605,18 @@ __device__ void sweep(const U8Job &J, const Sweep &g)
     const unsigned ldx = lc.ldx, hx = lc.hx;
     const bool fix_right = FAST ? false : g.fix_right;
     const bool fix_left = FAST ? false : g.fix_left;
-    const EdgeFix efix = edge_fix<PPL, OFF>(lane16, xo, W, EDGE && g.fix_left, EDGE && g.fix_right);
+    const EdgeFix efix = edge_fix<PPL, OFF, BM>(lane16, xo, W, EDGE && g.fix_left, EDGE && g.fix_right);
 
     const GMEM uint8_t *src = (const GMEM uint8_t *)J.src;
     const int64_t pitch = J.src_pitch;
-    auto rowp = [&](int t) { return src + (int64_t)clampi(yin0 + t, 0, ymax) * pitch; };
+    // input row of slot t under the border rule (zero border: the nearest
+    // row, whose bytes row_in() then discards)
+    auto row_of = [&](int t) {
+        if constexpr (BM == kBmRefl) return reflect101(yin0 + t, J.H);
+        else return clampi(yin0 + t, 0, ymax);
+    };
+    auto row_in = [&](int t) { return (unsigned)(yin0 + t) <= (unsigned)ymax; };
+    auto rowp = [&](int t) { return src + (int64_t)row_of(t) * pitch; };
 
     // Rings indexed by input row mod 5 (A2 and B by the row they are centred
     // on).  Live ranges are short: an unpacked row lives 3 steps, v_s (A2) and
@@ -527,11 +636,18 @@ __device__ void sweep(const U8Job &J, const Sweep &g)
     };
     auto process = [&](int t, RawRow<PPL> &r, v2s (&R)[NP + 4], v2s (&hr)[NP], v2s (&hs)[NP]) {
         Win<PPL> w;
-        if constexpr (EDGE) apply_edge<PPL>(r, efix);
+        if constexpr (ALIGNED && BM == kBmZero) {
+            if (!row_in(t)) {
+#pragma unroll
+                for (int m = 0; m < PPL / 4; ++m) r.d[m] = 0;
+                r.hw = 0;
+            }
+        }
+        if constexpr (EDGE) apply_edge<PPL, BM>(r, efix);
         if constexpr (ALIGNED)
-            w = finish_row<PPL, OFF>(r, lane16, xo, W, fix_right, fix_left);
+            w = finish_row<PPL, OFF, BM>(r, lane16, xo, W, fix_right, fix_left);
         else
-            w = load_row_bytes<PPL>(rowp(t), xo, W);
+            w = load_row_bytes<PPL, BM>(rowp(t), xo, W, row_in(t));
         unpack<PPL, OFF>(w, R);
         row_filters<NP>(R, hr, hs);
     };
@@ -633,7 +749,7 @@ constexpr int single_waves(int ppl, int opr, bool aligned, bool dir)
 // side, so all groups walk the same rows and row addresses stay scalar) and
 // the (w % nchunk)-th of nchunk equal row ranges of it: every resident wave
 // gets the same amount of work and there is no tail of a second round.
-template <int PPL, int OFF, bool ALIGNED, bool DIR, int OPR>
+template <int PPL, int OFF, bool ALIGNED, bool DIR, int OPR, int BM>
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
     single_waves(PPL, OPR, ALIGNED, DIR), single_waves(PPL, OPR, ALIGNED, DIR)))) void k_u8_single(U8Job J, int nchunk)
 {
@@ -659,18 +775,18 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
     // fix-ups of their group halos
     const bool fast = ALIGNED && (strip * 4 + 4) * TW <= J.Wo;
     if (fast && !g.fix_right && !g.fix_left)
-        sweep<PPL, OFF, ALIGNED, DIR, true, false, OPR>(J, g);
+        sweep<PPL, OFF, ALIGNED, DIR, true, false, OPR, BM>(J, g);
     else if (fast)
-        sweep<PPL, OFF, ALIGNED, DIR, true, true, OPR>(J, g);
+        sweep<PPL, OFF, ALIGNED, DIR, true, true, OPR, BM>(J, g);
     else
-        sweep<PPL, OFF, ALIGNED, DIR, false, false, OPR>(J, g);
+        sweep<PPL, OFF, ALIGNED, DIR, false, false, OPR, BM>(J, g);
 }
 
 
-template <int PPL, int OFF, bool ALIGNED, bool DIR, int OPR>
+template <int PPL, int OFF, bool ALIGNED, bool DIR, int OPR, int BM>
 const void *single_fn()
 {
-    return reinterpret_cast<const void *>(&k_u8_single<PPL, OFF, ALIGNED, DIR, OPR>);
+    return reinterpret_cast<const void *>(&k_u8_single<PPL, OFF, ALIGNED, DIR, OPR, BM>);
 }
 
 // Resident waves of a kernel on this device (cached per kernel).
@@ -691,11 +807,19 @@ int resident_waves(const void *fn)
     return w;
 }
 
-template <int PPL, int OFF, bool DIR, int OPR>
+// Reflect-101 on an image narrower than 3 columns folds more than once:
+// such images take the byte path, whose column map is the general fold.
+template <int BM>
+bool vector_path_ok(const U8Job &j)
+{
+    return u8_rows_aligned(j) && !(BM == kBmRefl && j.W < 3);
+}
+
+template <int PPL, int OFF, bool DIR, int OPR, int BM>
 hipError_t launch_single_t(const U8Job &j, const U8Shape &s, hipStream_t st)
 {
-    const bool aligned = u8_rows_aligned(j);
-    const void *fn = aligned ? single_fn<PPL, OFF, true, DIR, OPR>() : single_fn<PPL, OFF, false, DIR, OPR>();
+    const bool aligned = vector_path_ok<BM>(j);
+    const void *fn = aligned ? single_fn<PPL, OFF, true, DIR, OPR, BM>() : single_fn<PPL, OFF, false, DIR, OPR, BM>();
     const int ntxw = (j.ntx + 3) / 4;
     int slots = s.waves > 0 ? s.waves : resident_waves(fn);
     if (slots <= 0) slots = 2048;
@@ -707,6 +831,28 @@ hipError_t launch_single_t(const U8Job &j, const U8Shape &s, hipStream_t st)
     U8Job jj = j;
     void *args[] = {(void *)&jj, (void *)&nchunk};
     return hipLaunchKernel(fn, dim3(grid), dim3(64 * kWaves), args, 0, st);
+}
+
+template <int PPL, int OFF, int OPR, int BM>
+hipError_t launch_single_d(const U8Job &j, const U8Shape &s, hipStream_t st)
+{
+    return j.dir_type ? launch_single_t<PPL, OFF, true, OPR, BM>(j, s, st)
+                      : launch_single_t<PPL, OFF, false, OPR, BM>(j, s, st);
+}
+
+// Single-image launch of operator OPR under border rule BM; with kBmRep,
+// `valid` selects the VALID border (output centred at offset VOFF, the
+// operator's radius).  A translation unit compiles the kernels of the rules
+// it calls this with.
+template <int OPR, int VOFF, int BM>
+hipError_t launch_single_border(const U8Job &j, bool valid, const U8Shape &s, hipStream_t st)
+{
+    if (j.ntx <= 0 || j.Ho <= 0) return hipSuccess;
+    if constexpr (BM == kBmRep) {
+        if (valid)
+            return s.ppl == 16 ? launch_single_d<16, VOFF, OPR, BM>(j, s, st) : launch_single_d<8, VOFF, OPR, BM>(j, s, st);
+    }
+    return s.ppl == 16 ? launch_single_d<16, 0, OPR, BM>(j, s, st) : launch_single_d<8, 0, OPR, BM>(j, s, st);
 }
 
 }  // namespace

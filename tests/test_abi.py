@@ -58,7 +58,12 @@ def test_validate_u8(sobel_lib):
     assert v_u8(api, w=0) == api.EINVAL
     assert v_u8(api, h=-1) == api.EINVAL
     assert v_u8(api, pitch=63) == api.EINVAL
-    assert v_u8(api, border=2) == api.EINVAL
+    assert v_u8(api, border=4) == api.EINVAL
+    assert v_u8(api, border=-1) == api.EINVAL
+    for b in (2, 3):                                          # ZERO, REFLECT101: H x W output
+        assert v_u8(api, border=b) == 0
+        assert v_u8(api, border=b, w=1, h=1, pitch=1, mag_pitch=1) == 0
+        assert v_u8(api, border=b, mag_pitch=63) == api.EINVAL
     assert v_u8(api, border=1, w=4) == api.EINVAL            # VALID needs >= 5
     assert v_u8(api, border=1, w=5, h=5, pitch=5, mag_pitch=1) == 0
     assert v_u8(api, mag_pitch=10) == api.EINVAL
@@ -129,6 +134,44 @@ def test_validate_batch(sobel_lib):
     arr[1].mag = FAKE + 11 * (1 << 24)
     arr[2].width = 300                               # pitch too small
     assert api.lib.sobel4x5_validate_batch(arr, 3, 0) == api.EINVAL
+    arr[2].width = 102
+    for b in (2, 3):
+        assert api.lib.sobel4x5_validate_batch(arr, 3, b) == 0
+
+
+def test_validate_batch_with_outputs(sobel_lib):
+    """Per-image outputs: directional planes take part in every overlap check,
+    and imgs[i].mag is ignored."""
+    api = sobel_lib
+    n = 3
+    arr = (api.Image * n)()
+    outs = (api.Outputs * n)()
+    for i in range(n):
+        arr[i].src = FAKE + i * (1 << 24)
+        arr[i].mag = 0                                  # ignored with outputs
+        arr[i].width, arr[i].height = 100, 50
+        arr[i].src_pitch = 128
+        outs[i].mag = FAKE + (10 + i) * (1 << 24)
+        outs[i].mag_pitch = 128
+        outs[i].dir_type = 1
+        outs[i].dir_pitch = 256
+        for k in range(4):
+            outs[i].dir[k] = FAKE + (20 + 4 * i + k) * (1 << 24)
+    v = api.lib.sobel4x5_validate_batch_ex
+    assert v(arr, outs, n, 0) == 0
+    assert v(arr, None, n, 0) == api.EINVAL             # plain batch: mag must be given
+    outs[2].dir[3] = outs[0].dir[1] + 64                # planes of two images overlap
+    assert v(arr, outs, n, 0) == api.EINVAL
+    outs[2].dir[3] = arr[1].src                         # a plane overlaps an input
+    assert v(arr, outs, n, 0) == api.EINVAL
+    outs[2].dir[3] = FAKE + 40 * (1 << 24)
+    outs[1].dir_pitch = 100                             # pitch below 2 * width
+    assert v(arr, outs, n, 0) == api.EINVAL
+    outs[1].dir_pitch = 256
+    outs[0].mag = 0                                     # planes only
+    assert v(arr, outs, n, 3) == 0
+    outs[0].dir_type = 0                                # nothing requested for image 0
+    assert v(arr, outs, n, 0) == api.EINVAL
 
 
 def test_validate_f32(sobel_lib):
@@ -142,6 +185,8 @@ def test_validate_f32(sobel_lib):
     assert f(src, 2, 64, 32, 256, 256 * 32, 0, src + 64, 256, 256 * 32) == api.EINVAL  # overlap
     assert f(src, 1, 4, 4, 16, 0, 1, out, 16, 0) == api.EINVAL                     # VALID < 5
     assert f(src, 0, 8, 8, 32, 0, 0, out, 32, 0) == 0                               # empty batch
+    for b in (2, 3):                                                                  # uint8 path only
+        assert f(src, 2, 64, 32, 256, 256 * 32, b, out, 256, 256 * 32) == api.EUNSUPPORTED
 
 
 def test_plan_handles_are_checked(sobel_lib):

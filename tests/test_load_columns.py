@@ -65,3 +65,45 @@ def test_every_load_holds_a_byte_of_the_row(tmp_path):
     subprocess.run(["g++", "-std=c++17", "-O1", "-I", str(CSRC), str(src), "-o", str(exe)], check=True)
     r = subprocess.run([str(exe)], capture_output=True, text=True)
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout
+
+
+FOLD_PROGRAM = r"""
+#include <cstdio>
+#include "load_columns.hpp"
+using namespace s4x5;
+// the definition, written out: step by one pixel, bouncing off both edges
+static int walk(int i, int n) {
+    if (n == 1) return 0;
+    int pos = 0, dir = i >= 0 ? 1 : -1;
+    for (int k = 0; k != (i >= 0 ? i : -i); ++k) {
+        if (pos + dir < 0 || pos + dir > n - 1) dir = -dir;
+        pos += dir;
+    }
+    return pos;
+}
+int main() {
+    int bad = 0;
+    for (int n = 1; n <= 70; ++n)
+        for (int i = -3 * n - 5; i <= 4 * n + 5; ++i) {
+            const int r = reflect101(i, n);
+            if (r < 0 || r >= n || r != walk(i, n)) {
+                if (bad < 10) std::printf("BAD n=%d i=%d got %d want %d\n", n, i, r, walk(i, n));
+                ++bad;
+            }
+        }
+    std::printf(bad ? "FAIL %d\n" : "ok\n", bad);
+    return bad != 0;
+}
+"""
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_reflect101_index_map(tmp_path):
+    """The kernels' reflect-101 map stays inside [0, n-1] for every index and
+    equals a walk that bounces off both edges without repeating them."""
+    src = tmp_path / "fold.cpp"
+    src.write_text(FOLD_PROGRAM)
+    exe = tmp_path / "fold"
+    subprocess.run(["g++", "-std=c++17", "-O1", "-I", str(CSRC), str(src), "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout
