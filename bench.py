@@ -7,7 +7,8 @@ Infinity Cache cannot serve them.  Secondary results (mixed-size batch in one
 persistent launch vs per-image launches, fp32 forward+backward, the size /
 output-type sweep) are reported in extra keys of the same JSON line.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--only u8,copy,sweep,ops,batched,f32,weighted,pipe]
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+                [--only u8,copy,sweep,ops,borders,batched,f32,weighted,pipe]
                 [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -42,14 +43,16 @@ def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=200)
-    p.add_argument("--warmup", type=int, default=20)
+    # the first ~200 launches run at lower clocks (measured: 62 us against 54 us
+    # per 8192^2 launch), so the default warm-up covers them
+    p.add_argument("--warmup", type=int, default=400)
     p.add_argument("--only", default=None,
-                   help="comma-separated subset of: u8, copy, sweep, ops, batched, f32, weighted, pipe")
+                   help="comma-separated subset of: u8, copy, sweep, ops, borders, batched, f32, weighted, pipe")
     p.add_argument("--no-cpu-baseline", action="store_true")
     a = p.parse_args()
     if a.only is not None:
         a.only = set(x.strip() for x in a.only.split(",") if x.strip())
-        bad = a.only - {"u8", "copy", "sweep", "ops", "batched", "f32", "weighted", "pipe"}
+        bad = a.only - {"u8", "copy", "sweep", "ops", "borders", "batched", "f32", "weighted", "pipe"}
         if bad:
             p.error("unknown --only part(s): %s" % ", ".join(sorted(bad)))
     return a
@@ -230,6 +233,50 @@ def bench_batched(torch, api, synth, dev, steps, warmup):
     del srcs, mags, g
     torch.cuda.empty_cache()
     return res
+
+
+def bench_borders(torch, api, synth, dev, steps, warmup):
+    """Border rules on the 8192^2 magnitude (replicate, zero, reflect-101),
+    and the 256-image batch with int16 directional planes as well as
+    magnitudes (2 + 8 = 10 B/px) in one persistent launch, per border."""
+    out = {}
+    img = synth.rect_image(N, N, 3)
+    nsets = max(2, ROTATE_BYTES // (2 * N * N))
+    base = torch.from_numpy(img).to(dev)
+    srcs = [base.clone() for _ in range(nsets)]
+    mags = [torch.empty((N, N), dtype=torch.uint8, device=dev) for _ in range(nsets)]
+    names = {api.BORDER_REPLICATE: "replicate", api.BORDER_ZERO: "zero", api.BORDER_REFLECT101: "reflect101"}
+    for b, name in names.items():
+        fn = lambda i, b=b: api.sobel4x5_u8(srcs[i % nsets], b, mag=mags[i % nsets])
+        ms = time_launches(torch, fn, steps, warmup)
+        out["8192_mag_" + name] = {"ms": round(ms, 5), "gpx_per_s": round(N * N / (ms * 1e-3) / 1e9, 2)}
+    del srcs, mags, base
+    torch.cuda.empty_cache()
+    sizes = synth.batch_sizes(256, 77)
+    imgs = [synth.rect_image(h, w, 1000 + i) for i, (h, w) in enumerate(sizes)]
+    px = sum(h * w for h, w in sizes)
+    srcs = []
+    for m in imgs:
+        h, w = m.shape
+        pitch = synth.round_up(w, 256)
+        flat = torch.empty(((h - 1) * pitch + w,), dtype=torch.uint8, device=dev)
+        v = flat.as_strided((h, w), (pitch, 1))
+        v.copy_(torch.from_numpy(m))
+        srcs.append(v)
+    mags = [torch.empty(m.shape, dtype=torch.uint8, device=dev) for m in imgs]
+    dirs = [[torch.empty(m.shape, dtype=torch.int16, device=dev) for _ in range(4)] for m in imgs]
+    k = max(5, steps // 10)
+    for b, name in names.items():
+        plan = api.Plan(srcs, mags, b, dir_type=api.DIR_S16, dirs=dirs)
+        ms = time_launches(torch, lambda i: plan.launch(), k, 3)
+        gbs = 10 * px / (ms * 1e-3) / 1e9
+        out["batch256_mag_dir_s16_" + name] = {"ms": round(ms, 4), "gpx_per_s": round(px / ms / 1e6, 2),
+                                               "alg_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                                               "tile": plan.info()}
+        plan.close()
+    del srcs, mags, dirs
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_f32(torch, api, synth, dev, steps, warmup):
@@ -414,6 +461,9 @@ def main():
     if want("ops"):
         log("operator comparison (4-dir 5x5, 2-dir 5x5, 2-dir 3x3)")
         line["ops"] = bench_ops(torch, api, synth, dev, args.steps, args.warmup)
+    if want("borders"):
+        log("border rules 8192x8192; 256-image batch with directional planes")
+        line["borders"] = bench_borders(torch, api, synth, dev, args.steps, args.warmup)
     if want("batched"):
         log("batched 256 images")
         line["batched"] = bench_batched(torch, api, synth, dev, args.steps, args.warmup)

@@ -655,12 +655,23 @@ __device__ void sweep(const U8Job &J, const Sweep &g)
     // prologue: rows t = 0..4 in flight, rows 0..3 processed (which frees
     // their slots), then rows 5 .. 3 + kPD.  Row t always lives in raw[t % 5].
     static_assert(kPD >= 1 && kPD <= 4, "prefetch distance must fit the 5-slot ring");
+    // The loads stay in row order (scheduling barriers): the loop's first
+    // step consumes row 4 and its wait is merged with the steady state at
+    // the loop header, so row 4 has to be older than rows 5 .. 3 + kPD.  Left
+    // free, the scheduler sinks row 4's load below the processing of rows
+    // 0..3 and after the later rows, and the merged wait drains every row in
+    // flight once per five rows.
 #pragma unroll
     for (int t = 0; t < 5; ++t) fetch_if(t, raw[t]);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int t = 0; t < 4; ++t) process(t, raw[t], Rr[t], HR[t], HS[t]);
 #pragma unroll
-    for (int t = 5; t < 4 + kPD; ++t) fetch_if(t, raw[t % 5]);
+    for (int t = 5; t < 4 + kPD; ++t) {
+        __builtin_amdgcn_sched_barrier(0);
+        fetch_if(t, raw[t % 5]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < NP + 4; ++c) {
         A2r[1][c] = Rr[2][c] - Rr[0][c];        // v_s centred on row 1
@@ -703,18 +714,28 @@ __device__ void sweep(const U8Job &J, const Sweep &g)
     using P2 = std::integral_constant<int, 2>;
     using P3 = std::integral_constant<int, 3>;
     using P4 = std::integral_constant<int, 4>;
-    // (a main loop of whole 5-step blocks plus a remainder keeps ~80 more
-    // values live across the loop exit; the uniform breaks cost two SALU ops)
-    for (int i = 0; i < niter; i += 5) {
+    // Whole 5-step blocks in a loop with one exit, then the 0..4 remaining
+    // steps after it.  Exits from inside the loop become flow blocks with an
+    // edge back to the loop header; the memory-wait analysis merges their
+    // state (a row loaded one step earlier) into the header and waits for
+    // every row in flight there, once per five rows.
+    const int nfull = niter - niter % 5;
+    for (int i = 0; i < nfull; i += 5) {
         step(i, P0{});
-        if (i + 1 >= niter) break;
         step(i + 1, P1{});
-        if (i + 2 >= niter) break;
         step(i + 2, P2{});
-        if (i + 3 >= niter) break;
         step(i + 3, P3{});
-        if (i + 4 >= niter) break;
         step(i + 4, P4{});
+    }
+    if (nfull < niter) {
+        step(nfull, P0{});
+        if (nfull + 1 < niter) {
+            step(nfull + 1, P1{});
+            if (nfull + 2 < niter) {
+                step(nfull + 2, P2{});
+                if (nfull + 3 < niter) step(nfull + 3, P3{});
+            }
+        }
     }
 }
 
