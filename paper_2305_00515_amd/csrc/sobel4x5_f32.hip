@@ -141,6 +141,34 @@ __device__ __forceinline__ float scale_of(float g, float S)
 template <int P>
 using Ph = std::integral_constant<int, P>;
 
+// Steps 0 .. T-1 of a five-slot ring: whole blocks of five in a loop with a
+// single exit, then the 0..4 remaining steps.  (Breaking out of the loop
+// after any step makes flow blocks with edges back to the loop header; the
+// memory-wait analysis merges their state into the header and waits there
+// for every row in flight.)
+template <class Step>
+__device__ __forceinline__ void run_steps(int T, Step &step)
+{
+    const int nfull = T - T % 5;
+    for (int t = 0; t < nfull; t += 5) {
+        step(t, Ph<0>{});
+        step(t + 1, Ph<1>{});
+        step(t + 2, Ph<2>{});
+        step(t + 3, Ph<3>{});
+        step(t + 4, Ph<4>{});
+    }
+    if (nfull < T) {
+        step(nfull, Ph<0>{});
+        if (nfull + 1 < T) {
+            step(nfull + 1, Ph<1>{});
+            if (nfull + 2 < T) {
+                step(nfull + 2, Ph<2>{});
+                if (nfull + 3 < T) step(nfull + 3, Ph<3>{});
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- forward
 // Wave (image b, strip s, chunk k): output columns [s*124, s*124+124),
 // output rows [o0, o1).  Lane l holds output columns s*124 - 2 + 2l + {0, 1}
@@ -175,8 +203,12 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_fwd(F32Args a, int 
 #pragma unroll
     for (int i = 0; i < 5; ++i) X[i] = HR[i] = HS[i] = pf[i] = F2{0.f, 0.f};
     constexpr int PD = 3;   // rows loaded ahead
+    // prologue loads in row order (the loop's first steps consume them)
 #pragma unroll
-    for (int t = 0; t < PD; ++t) pf[t] = ld(t);
+    for (int t = 0; t < PD; ++t) {
+        pf[t] = ld(t);
+        __builtin_amdgcn_sched_barrier(0);
+    }
 
     auto step = [&](int t, auto phase) {
         constexpr int p = decltype(phase)::value;
@@ -196,17 +228,7 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_fwd(F32Args a, int 
         if (keep_a) row[0] = mag_of(Gx.a, Gy.a, Gp.a, Gm.a);
         if (keep_b) row[1] = mag_of(Gx.b, Gy.b, Gp.b, Gm.b);
     };
-    for (int t = 0; t < T; t += 5) {
-        step(t, Ph<0>{});
-        if (t + 1 >= T) break;
-        step(t + 1, Ph<1>{});
-        if (t + 2 >= T) break;
-        step(t + 2, Ph<2>{});
-        if (t + 3 >= T) break;
-        step(t + 3, Ph<3>{});
-        if (t + 4 >= T) break;
-        step(t + 4, Ph<4>{});
-    }
+    run_steps(T, step);
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -267,10 +289,12 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
     for (int i = 0; i < 5; ++i)
         X[i] = HR[i] = HS[i] = WY[i] = WP[i] = AX[i] = AM[i] = AS[i] = pfx[i] = pfg[i] = F2{0.f, 0.f};
     constexpr int PD = 3;
+    // prologue loads in row order (the loop's first steps consume them)
 #pragma unroll
     for (int t = 0; t < PD; ++t) {
         pfx[t] = ldx(t);
         pfg[t] = ldg(t);
+        __builtin_amdgcn_sched_barrier(0);
     }
     F2 acc_top{0.f, 0.f}, acc_bot{0.f, 0.f};
 
@@ -344,17 +368,7 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
                 store(pr, v);
         }
     };
-    for (int t = 0; t < T; t += 5) {
-        step(t, Ph<0>{});
-        if (t + 1 >= T) break;
-        step(t + 1, Ph<1>{});
-        if (t + 2 >= T) break;
-        step(t + 2, Ph<2>{});
-        if (t + 3 >= T) break;
-        step(t + 3, Ph<3>{});
-        if (t + 4 >= T) break;
-        step(t + 4, Ph<4>{});
-    }
+    run_steps(T, step);
 }
 
 // Resident waves of a kernel (cached per kernel).

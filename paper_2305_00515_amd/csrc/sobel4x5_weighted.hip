@@ -84,24 +84,34 @@ __global__ __launch_bounds__(64 * kWavesW) void k_u8_weighted(WJob J, int nstrip
         const GMEM uint8_t *row = src + (int64_t)rr * J.src_pitch;
 #pragma unroll
         for (int j = 0; j < kPplW + 4; ++j) v[j] = row[col[j]];
-        if constexpr (BM == 1) {
-            const bool rin = (unsigned)r <= (unsigned)(J.H - 1);
-#pragma unroll
-            for (int j = 0; j < kPplW + 4; ++j) v[j] = (rin && ((colin >> j) & 1u)) ? v[j] : (uint8_t)0;
-        }
+    };
+    // zero border: which bytes of step t's row lie inside the image (applied
+    // when the row enters the ring, so that the loads stay in flight)
+    auto inside = [&](int t) -> u32 {
+        const int r = r0 + min(t, T - 1);
+        return (unsigned)r <= (unsigned)(J.H - 1) ? colin : 0u;
     };
 
     // bytes, so that every pair difference is known to fit 24 bits
     uint8_t ring[5][kPplW + 4], pf[5][kPplW + 4];
     constexpr int PD = 2;   // rows loaded ahead
 #pragma unroll
-    for (int t = 0; t < PD; ++t) ldrow(t, pf[t]);
+    for (int t = 0; t < PD; ++t) {
+        ldrow(t, pf[t]);
+        __builtin_amdgcn_sched_barrier(0);   // prologue rows in row order
+    }
 
     auto step = [&](int t, auto phase) {
         constexpr int p = decltype(phase)::value;
         ldrow(t + PD, pf[(p + PD) % 5]);
+        if constexpr (BM == 1) {
+            const u32 in = inside(t);
 #pragma unroll
-        for (int j = 0; j < kPplW + 4; ++j) ring[p][j] = pf[p][j];
+            for (int j = 0; j < kPplW + 4; ++j) ring[p][j] = ((in >> j) & 1u) ? pf[p][j] : (uint8_t)0;
+        } else {
+#pragma unroll
+            for (int j = 0; j < kPplW + 4; ++j) ring[p][j] = pf[p][j];
+        }
         if (t < 4) return;
         // window row i (0..4) = input row t - 4 + i, in slot (p + 1 + i) % 5
         const int yo = y0 + t - 4;
@@ -163,16 +173,26 @@ __global__ __launch_bounds__(64 * kWavesW) void k_u8_weighted(WJob J, int nstrip
             }
         }
     };
-    for (int t = 0; t < T; t += 5) {
+    // whole blocks of five steps in a loop with a single exit, then the
+    // 0..4 remaining steps (breaking out after any step makes flow blocks
+    // whose state the memory-wait analysis merges into the loop header)
+    const int nfull = T - T % 5;
+    for (int t = 0; t < nfull; t += 5) {
         step(t, PhW<0>{});
-        if (t + 1 >= T) break;
         step(t + 1, PhW<1>{});
-        if (t + 2 >= T) break;
         step(t + 2, PhW<2>{});
-        if (t + 3 >= T) break;
         step(t + 3, PhW<3>{});
-        if (t + 4 >= T) break;
         step(t + 4, PhW<4>{});
+    }
+    if (nfull < T) {
+        step(nfull, PhW<0>{});
+        if (nfull + 1 < T) {
+            step(nfull + 1, PhW<1>{});
+            if (nfull + 2 < T) {
+                step(nfull + 2, PhW<2>{});
+                if (nfull + 3 < T) step(nfull + 3, PhW<3>{});
+            }
+        }
     }
 }
 
