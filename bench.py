@@ -27,10 +27,13 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 # lane operations per second (one VALU instruction of a wave64 occupies a SIMD
 # for 4 cycles).  Packed int16 instructions count once: they are one issue.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# VALU instructions per output pixel of the magnitude-only interior path:
-# 1764 in the 5-row unrolled loop body of k_u8_single<16, replicate, aligned,
-# mag-only>, which makes 5 rows x 16 pixels per lane (counted in its ISA).
-U8_VALU_OPS_PER_PX = 1764 / 80.0
+# VALU issue slots per output pixel of the magnitude-only interior path: the
+# 5-row loop body of k_u8_single<16, replicate, aligned, mag-only>, which makes
+# 5 rows x 16 pixels per lane, holds 1791 VALU instructions (counted in its
+# ISA), 80 of them v_sqrt_f32, which issues at half rate (measured: 8.5 cycles
+# per wave instruction against 4.5 for v_fma_f32) and so takes two slots.
+U8_VALU_INSTR_PER_PX = 1791 / 80.0
+U8_VALU_OPS_PER_PX = (1791 + 80) / 80.0
 N = 8192
 ROTATE_BYTES = 2 << 30         # >= 1 GiB of distinct buffers (Infinity Cache is 256 MB)
 
@@ -448,7 +451,8 @@ def main():
                          "unit": "TOP/s", "frac": round(tops / VALU_PEAK_TOPS, 4),
                          "traffic": u8_traffic(),
                          "kernel": "k_u8_single<16,replicate,aligned,mag-only>",
-                         "valu_ops_per_px": round(U8_VALU_OPS_PER_PX, 3),
+                         "valu_slots_per_px": round(U8_VALU_OPS_PER_PX, 3),
+                         "valu_instr_per_px": round(U8_VALU_INSTR_PER_PX, 3),
                          "alg_bytes_per_launch": r["alg_bytes"], "hbm_GBps": round(gbs, 1),
                          "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)},
         })

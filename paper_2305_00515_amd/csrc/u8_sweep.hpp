@@ -588,8 +588,12 @@ struct Sweep {
 // niter rows, every lane's block and outputs inside the image, 16-byte
 // aligned input rows (EDGE: with the group-halo fix-ups of an image edge):
 // the loop body has no branches, so the compiler can schedule across steps.
-template <int PPL, int OFF, bool ALIGNED, bool DIR, bool FAST, bool EDGE, int OPR, int BM>
-__device__ void sweep(const U8Job &J, const Sweep &g)
+// BLOCKS: whole 5-step blocks in a single-exit loop plus a tail (long row
+// ranges); otherwise one loop that leaves after any step (short row ranges
+// of the batched kernel, where the tail's extra code costs more than the
+// waits it saves).
+template <int PPL, int OFF, bool ALIGNED, bool DIR, bool FAST, bool EDGE, int OPR, int BM, bool BLOCKS = true>
+__device__ __forceinline__ void sweep(const U8Job &J, const Sweep &g)
 {
     static_assert(!EDGE || FAST, "edge fix-ups by mask exist for fast waves only");
     constexpr int NP = PPL / 2;
@@ -719,6 +723,20 @@ __device__ void sweep(const U8Job &J, const Sweep &g)
     // edge back to the loop header; the memory-wait analysis merges their
     // state (a row loaded one step earlier) into the header and waits for
     // every row in flight there, once per five rows.
+    if constexpr (!BLOCKS) {
+        for (int i = 0; i < niter; i += 5) {
+            step(i, P0{});
+            if (i + 1 >= niter) break;
+            step(i + 1, P1{});
+            if (i + 2 >= niter) break;
+            step(i + 2, P2{});
+            if (i + 3 >= niter) break;
+            step(i + 3, P3{});
+            if (i + 4 >= niter) break;
+            step(i + 4, P4{});
+        }
+        return;
+    }
     const int nfull = niter - niter % 5;
     for (int i = 0; i < nfull; i += 5) {
         step(i, P0{});
