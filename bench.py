@@ -213,7 +213,7 @@ def bench_batched(torch, api, synth, dev, steps, warmup):
     px = sum(h * w for h, w in sizes)
     plan = api.Plan(srcs, mags, autotune=True)
     k = max(5, steps // 10)
-    ms_plan = time_launches(torch, lambda i: plan.launch(), k, 3)
+    ms_plan = time_launches(torch, lambda i: plan.launch(), k, 20)
 
     def per_image(i):
         for s, m in zip(srcs, mags):
@@ -271,7 +271,7 @@ def bench_borders(torch, api, synth, dev, steps, warmup):
     k = max(5, steps // 10)
     for b, name in names.items():
         plan = api.Plan(srcs, mags, b, dir_type=api.DIR_S16, dirs=dirs)
-        ms = time_launches(torch, lambda i: plan.launch(), k, 3)
+        ms = time_launches(torch, lambda i: plan.launch(), k, 20)
         gbs = 10 * px / (ms * 1e-3) / 1e9
         out["batch256_mag_dir_s16_" + name] = {"ms": round(ms, 4), "gpx_per_s": round(px / ms / 1e6, 2),
                                                "alg_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
@@ -289,8 +289,8 @@ def bench_f32(torch, api, synth, dev, steps, warmup):
     gm = torch.full_like(x, 1.0 / x.numel())
     dx = torch.empty_like(x)
     k = max(5, steps // 10)
-    ms_f = time_launches(torch, lambda i: api.sobel4x5_f32_fwd(x, out=M), k, 3)
-    ms_b = time_launches(torch, lambda i: api.sobel4x5_f32_bwd(x, gm, out=dx), k, 3)
+    ms_f = time_launches(torch, lambda i: api.sobel4x5_f32_fwd(x, out=M), k, max(3, warmup))
+    ms_b = time_launches(torch, lambda i: api.sobel4x5_f32_bwd(x, gm, out=dx), k, max(3, warmup // 2))
     px = B * H * W
     res = {"batch": B, "H": H, "W": W, "fwd_ms": round(ms_f, 4), "bwd_ms": round(ms_b, 4),
            "fwd_bwd_gpx_per_s": round(px / ((ms_f + ms_b) * 1e-3) / 1e9, 2),
@@ -353,7 +353,7 @@ def bench_copy(torch, api, dev, steps):
     b = torch.empty(n, dtype=torch.uint8, device=dev)
     a.fill_(7)
     k = max(3, steps // 20)
-    ms = time_launches(torch, lambda i: api.debug_copy(a, b) if i % 2 == 0 else api.debug_copy(b, a), k, 2)
+    ms = time_launches(torch, lambda i: api.debug_copy(a, b) if i % 2 == 0 else api.debug_copy(b, a), k, 50)
     gbs = 2 * n / (ms * 1e-3) / 1e9
     del a, b
     torch.cuda.empty_cache()
@@ -364,7 +364,7 @@ def bench_copy(torch, api, dev, steps):
 # and WRITE_SIZE (KiB per dispatch), scaled by what the same counters read for
 # the plain copy kernel (sobel4x5_debug_copy) of known size.  Valid only for
 # the kernel source they were taken on (its SHA-256 prefix); None otherwise.
-U8_TRAFFIC = {"src_sha256": "95cc097372a3ce6f", "bytes": 144529085}   # profiles/k_u8_single_8192x8192_mag_u8.md
+U8_TRAFFIC = {"src_sha256": "b5da32620066652a", "bytes": 145197866}   # profiles/k_u8_single_8192x8192_mag_u8.md
 
 
 # Sources that define k_u8_single (the hash covers them in this order).
