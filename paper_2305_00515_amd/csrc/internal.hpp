@@ -100,6 +100,12 @@ struct WJob {
 hipError_t launch_u8_weighted(const WJob &j, hipStream_t stream);
 
 hipError_t launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t stream);
+
+// Fingerprint of one plane of `rows` rows of `row_bytes` bytes (device):
+// fingerprint_blocks(rows) workgroup sums written to `partials` (device).
+int64_t fingerprint_blocks(int64_t rows);
+hipError_t launch_fingerprint(const void *base, int64_t pitch, int64_t row_bytes, int64_t rows, uint64_t *partials,
+                              hipStream_t stream);
 hipError_t launch_round_mag(const int32_t *S, uint8_t *out, int64_t n, hipStream_t stream);
 
 // fp32 path (pointers and strides as in the public header).

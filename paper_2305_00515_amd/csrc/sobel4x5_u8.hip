@@ -25,6 +25,38 @@ __global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src, u
         if (base + 256 * k < n16) dst[base + 256 * k] = v[k];
 }
 
+// Order-independent fingerprint of one output plane (the autotuner's check
+// that a candidate tile shape reproduces the reference bytes): the byte at
+// (row r, column c) contributes mix(r, c, byte), with the splitmix64
+// finaliser as the mix; each workgroup sums (mod 2^64) the contributions of
+// kFpRows rows into out[blockIdx.x].
+constexpr int kFpRows = 16;
+
+__global__ __launch_bounds__(256) void k_fingerprint(const uint8_t *__restrict__ base, int64_t pitch,
+                                                     int64_t row_bytes, int64_t rows, uint64_t *__restrict__ out)
+{
+    const int64_t r0 = (int64_t)blockIdx.x * kFpRows;
+    const int64_t r1 = r0 + kFpRows < rows ? r0 + kFpRows : rows;
+    uint64_t acc = 0;
+    for (int64_t r = r0; r < r1; ++r) {
+        const uint8_t *row = base + r * pitch;
+        for (int64_t c = threadIdx.x; c < row_bytes; c += 256) {
+            uint64_t v = ((uint64_t)r << 40) ^ ((uint64_t)c << 8) ^ (uint64_t)row[c];
+            v = (v ^ (v >> 30)) * 0xbf58476d1ce4e5b9ull;
+            v = (v ^ (v >> 27)) * 0x94d049bb133111ebull;
+            acc += v ^ (v >> 31);
+        }
+    }
+    __shared__ uint64_t red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
 __global__ void k_round_mag(const int32_t *S, uint8_t *out, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -61,6 +93,19 @@ hipError_t launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t st
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<const uint4 *>(src),
                        static_cast<uint4 *>(dst), n16);
+    return hipGetLastError();
+}
+
+int64_t fingerprint_blocks(int64_t rows) { return (rows + kFpRows - 1) / kFpRows; }
+
+hipError_t launch_fingerprint(const void *base, int64_t pitch, int64_t row_bytes, int64_t rows, uint64_t *partials,
+                              hipStream_t st)
+{
+    const int64_t blocks = fingerprint_blocks(rows);
+    if (blocks <= 0 || row_bytes <= 0) return hipSuccess;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fingerprint, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<const uint8_t *>(base),
+                       pitch, row_bytes, rows, partials);
     return hipGetLastError();
 }
 

@@ -196,3 +196,37 @@ def test_fp32_rejects_the_new_borders(sobel_lib, gpu):
         with pytest.raises(sobel_lib.SobelError) as e:
             sobel_lib.sobel4x5_f32_fwd(x, b)
         assert e.value.code == sobel_lib.EUNSUPPORTED
+
+
+def test_batched_mixed_outputs_through_the_c_abi(oracle_mod, sobel_lib, gpu):
+    """One batch whose images ask for different outputs: magnitude only,
+    int16 planes only, magnitude + int32 planes, magnitude + int16 planes
+    (the C ABI's per-image sobel4x5_outputs)."""
+    api = sobel_lib
+    imgs = batch_images()[2:8]
+    kinds = [(True, 0), (False, 1), (True, 2), (True, 1), (False, 2), (True, 0)]
+    border = REFLECT101
+    n = len(imgs)
+    srcs = [dev_image(m, gpu, synth.round_up(m.shape[1], 16)) for m in imgs]
+    arr = (api.Image * n)()
+    outs = (api.Outputs * n)()
+    keep = []
+    for i, (m, s, (want_mag, dt)) in enumerate(zip(imgs, srcs, kinds)):
+        o, (h, w, p), res = api._u8_outputs(s, border, None, want_mag, dt, None)
+        outs[i] = o
+        arr[i].src = s.data_ptr()
+        arr[i].width, arr[i].height, arr[i].src_pitch = w, h, p
+        keep.append(res)
+    api._check(api.lib.sobel4x5_batched_ex(arr, outs, n, border, api._stream(srcs[0])), "sobel4x5_batched_ex")
+    torch.cuda.synchronize()
+    for m, (want_mag, dt), (g, planes) in zip(imgs, kinds, keep):
+        om, od = oracle_mod.sobel_u8(m, border)
+        if want_mag:
+            assert np.array_equal(g.cpu().numpy(), om), m.shape
+        else:
+            assert g is None
+        if dt:
+            d = np.stack([x.cpu().numpy() for x in planes]).astype(np.int32)
+            assert np.array_equal(d, od), m.shape
+        else:
+            assert planes is None
