@@ -180,7 +180,15 @@ U8Shape default_shape(int32_t Wo, int32_t Ho, int32_t dir_type)
     if (ppl == 8 || ppl == 16) s.ppl = ppl;
     s.th = 32;
     s.wpg = 4;
-    s.waves = env_int("SOBEL4X5_U8_WAVES", 0);
+    // Directional planes (up to 17 B/px) are bound by the stores: many short
+    // row ranges, 4 rows each, beat one round of resident waves (8192^2 int16
+    // planes: 487 against 432 Gpx/s).
+    if (dir_type != SOBEL4X5_DIR_NONE) {
+        s.waves = 1 << 30;
+        s.min_rows = 4;
+    }
+    const int waves = env_int("SOBEL4X5_U8_WAVES", 0);
+    if (waves > 0) s.waves = waves;
     const int mr = env_int("SOBEL4X5_U8_MIN_ROWS", 0);
     if (mr >= 1 && mr <= 64) s.min_rows = mr;
     return s;
@@ -719,8 +727,15 @@ int sobel4x5_u8_op(const uint8_t *src, int32_t width, int32_t height, int64_t sr
     }
     U8Job j = make_job(src, width, height, src_pitch, Wo, Ho, out->mag, out->mag_pitch,
                        out->dir_type ? dirs : nullptr, out->dir_pitch, out->dir_type);
-    const U8Shape s = default_shape(Wo, Ho, out->dir_type);
+    U8Shape s = default_shape(Wo, Ho, out->dir_type);
     u8_tile(j, s);
+    // The two-directional operators are lighter on arithmetic, so the 4-row
+    // prologue each wave re-reads weighs more: on large images they take
+    // 32-row ranges as long as 2048 waves remain (8192^2 3x3: 2128 -> 2232
+    // Gpx/s).
+    if (out->dir_type == SOBEL4X5_DIR_NONE && env_int("SOBEL4X5_U8_MIN_ROWS", 0) == 0 &&
+        (int64_t)((j.ntx + 3) / 4) * (Ho / 32) >= 2048)
+        s.min_rows = 32;
     hipError_t e = launch_u8_2dir(j, op, border, s, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_u8_op launch");
 }

@@ -862,9 +862,11 @@ hipError_t launch_single_t(const U8Job &j, const U8Shape &s, hipStream_t st)
     const int ntxw = (j.ntx + 3) / 4;
     int slots = s.waves > 0 ? s.waves : resident_waves(fn);
     if (slots <= 0) slots = 2048;
-    // equal row ranges per strip, at least s.min_rows rows each
+    // equal row ranges per strip, at least s.min_rows rows each, and at most
+    // 2^28 waves in all (the kernel numbers waves in 32 bits)
     int nchunk = std::max(1, slots / std::max(1, ntxw));
     nchunk = std::min(nchunk, std::max(1, j.Ho / std::max(1, s.min_rows)));
+    nchunk = std::min(nchunk, std::max(1, (1 << 28) / std::max(1, ntxw)));
     const int64_t waves = (int64_t)ntxw * nchunk;
     const int grid = (int)((waves + kWaves - 1) / kWaves);
     U8Job jj = j;
