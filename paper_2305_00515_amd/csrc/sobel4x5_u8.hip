@@ -3,7 +3,7 @@
 // (zero and reflect-101: sobel4x5_u8_border.hip), and a plain copy kernel
 // that serves as the bandwidth reference.
 
-#include "u8_sweep.hpp"
+#include "u8_launch.hpp"
 
 namespace s4x5 {
 namespace {

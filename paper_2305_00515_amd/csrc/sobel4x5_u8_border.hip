@@ -1,7 +1,7 @@
 // uint8 four-directional 5x5 kernel for the zero and reflect-101 borders:
 // the single-image launch of the sweep in u8_sweep.hpp.
 
-#include "u8_sweep.hpp"
+#include "u8_launch.hpp"
 
 namespace s4x5 {
 

@@ -9,7 +9,7 @@
 // operator, on (y + 2, x + 2).  This file holds the replicate and valid
 // borders; sobel_2dir_u8_border.hip the zero and reflect-101 ones.
 
-#include "u8_sweep.hpp"
+#include "u8_launch.hpp"
 
 namespace s4x5 {
 

@@ -2,7 +2,7 @@
 // the 0 / 90 deg pair of Eq. (sobel5_1)) for the zero and reflect-101
 // borders: the single-image launch of the sweep in u8_sweep.hpp.
 
-#include "u8_sweep.hpp"
+#include "u8_launch.hpp"
 
 namespace s4x5 {
 

@@ -822,79 +822,5 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
 }
 
 
-template <int PPL, int OFF, bool ALIGNED, bool DIR, int OPR, int BM>
-const void *single_fn()
-{
-    return reinterpret_cast<const void *>(&k_u8_single<PPL, OFF, ALIGNED, DIR, OPR, BM>);
-}
-
-// Resident waves of a kernel on this device (cached per kernel).
-int resident_waves(const void *fn)
-{
-    static std::mutex mu;
-    static std::vector<std::pair<const void *, int>> cache;
-    std::lock_guard<std::mutex> lk(mu);
-    for (auto &e : cache)
-        if (e.first == fn) return e.second;
-    int dev = 0, ncu = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * kWaves, 0) != hipSuccess)
-        return 0;
-    const int w = std::max(1, per_cu) * ncu * kWaves;
-    cache.emplace_back(fn, w);
-    return w;
-}
-
-// Reflect-101 on an image narrower than 3 columns folds more than once:
-// such images take the byte path, whose column map is the general fold.
-template <int BM>
-bool vector_path_ok(const U8Job &j)
-{
-    return u8_rows_aligned(j) && !(BM == kBmRefl && j.W < 3);
-}
-
-template <int PPL, int OFF, bool DIR, int OPR, int BM>
-hipError_t launch_single_t(const U8Job &j, const U8Shape &s, hipStream_t st)
-{
-    const bool aligned = vector_path_ok<BM>(j);
-    const void *fn = aligned ? single_fn<PPL, OFF, true, DIR, OPR, BM>() : single_fn<PPL, OFF, false, DIR, OPR, BM>();
-    const int ntxw = (j.ntx + 3) / 4;
-    int slots = s.waves > 0 ? s.waves : resident_waves(fn);
-    if (slots <= 0) slots = 2048;
-    // equal row ranges per strip, at least s.min_rows rows each, and at most
-    // 2^28 waves in all (the kernel numbers waves in 32 bits)
-    int nchunk = std::max(1, slots / std::max(1, ntxw));
-    nchunk = std::min(nchunk, std::max(1, j.Ho / std::max(1, s.min_rows)));
-    nchunk = std::min(nchunk, std::max(1, (1 << 28) / std::max(1, ntxw)));
-    const int64_t waves = (int64_t)ntxw * nchunk;
-    const int grid = (int)((waves + kWaves - 1) / kWaves);
-    U8Job jj = j;
-    void *args[] = {(void *)&jj, (void *)&nchunk};
-    return hipLaunchKernel(fn, dim3(grid), dim3(64 * kWaves), args, 0, st);
-}
-
-template <int PPL, int OFF, int OPR, int BM>
-hipError_t launch_single_d(const U8Job &j, const U8Shape &s, hipStream_t st)
-{
-    return j.dir_type ? launch_single_t<PPL, OFF, true, OPR, BM>(j, s, st)
-                      : launch_single_t<PPL, OFF, false, OPR, BM>(j, s, st);
-}
-
-// Single-image launch of operator OPR under border rule BM; with kBmRep,
-// `valid` selects the VALID border (output centred at offset VOFF, the
-// operator's radius).  A translation unit compiles the kernels of the rules
-// it calls this with.
-template <int OPR, int VOFF, int BM>
-hipError_t launch_single_border(const U8Job &j, bool valid, const U8Shape &s, hipStream_t st)
-{
-    if (j.ntx <= 0 || j.Ho <= 0) return hipSuccess;
-    if constexpr (BM == kBmRep) {
-        if (valid)
-            return s.ppl == 16 ? launch_single_d<16, VOFF, OPR, BM>(j, s, st) : launch_single_d<8, VOFF, OPR, BM>(j, s, st);
-    }
-    return s.ppl == 16 ? launch_single_d<16, 0, OPR, BM>(j, s, st) : launch_single_d<8, 0, OPR, BM>(j, s, st);
-}
-
 }  // namespace
 }  // namespace s4x5
