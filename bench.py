@@ -77,6 +77,27 @@ def time_launches(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+def warm(torch, fn, n):
+    """n untimed calls of fn(i), then a synchronisation."""
+    for i in range(n):
+        fn(i)
+    torch.cuda.synchronize()
+
+
+def per_launch_us(torch, fn, n):
+    """Median and minimum of n single-launch times (an event pair around each
+    launch, on the current stream), in microseconds."""
+    s = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for i, (a, b) in enumerate(ev):
+        a.record(s)
+        fn(i)
+        b.record(s)
+    torch.cuda.synchronize()
+    t = sorted(a.elapsed_time(b) * 1e3 for a, b in ev)
+    return {"median": round(t[n // 2], 2), "min": round(t[0], 2), "launches": n}
+
+
 def image_sets(torch, img, dev, nsets, pitch=None):
     h, w = img.shape
     base = torch.from_numpy(img).to(dev)
@@ -99,11 +120,12 @@ def bench_u8(torch, api, synth, dev, steps, warmup):
         api.sobel4x5_u8(srcs[k], mag=mags[k])
 
     ms = time_launches(torch, step, steps, warmup)
+    per = per_launch_us(torch, step, 50)
     hot = time_launches(torch, lambda i: api.sobel4x5_u8(srcs[0], mag=mags[0]), steps, warmup)
     px = N * N
     res = {
         "ms": ms, "gpx": px / (ms * 1e-3) / 1e9, "alg_bytes": 2 * px,
-        "hot_ms": hot, "nsets": nsets, "rotating_gib": nsets * 2 * px / 2 ** 30,
+        "hot_ms": hot, "nsets": nsets, "rotating_gib": nsets * 2 * px / 2 ** 30, "per_launch_us": per,
     }
     del srcs, mags
     torch.cuda.empty_cache()
@@ -112,6 +134,26 @@ def bench_u8(torch, api, synth, dev, steps, warmup):
 
 def bench_sweep(torch, api, synth, dev, steps, warmup):
     out = {}
+    # the field images (1080p and 4K, rows pitched to 2048 / 3840 bytes), magnitude only
+    for (h, w, pitch) in ((1080, 1920, 2048), (2160, 3840, 3840)):
+        img = synth.field_image(h, w, 1)
+        px = h * w
+        nsets = max(2, ROTATE_BYTES // (2 * pitch * h))
+        srcs = []
+        for _ in range(nsets):
+            flat = torch.empty((h * pitch,), dtype=torch.uint8, device=dev)
+            v = flat.as_strided((h, w), (pitch, 1))
+            v.copy_(torch.from_numpy(img))
+            srcs.append(v)
+        mags = [torch.empty((h, w), dtype=torch.uint8, device=dev) for _ in range(nsets)]
+        fn = lambda i: api.sobel4x5_u8(srcs[i % nsets], mag=mags[i % nsets])
+        warm(torch, fn, max(5, warmup))
+        # a launch lasts a few microseconds, less than a host call: graph replay
+        ms = time_graph(torch, fn, min(nsets, 200), max(2, steps // 20))
+        out["field_%dx%d_mag_u8" % (w, h)] = {"ms": round(ms, 5), "gpx_per_s": round(px / (ms * 1e-3) / 1e9, 2),
+                                             "timing": "graph replay"}
+        del srcs, mags
+        torch.cuda.empty_cache()
     for n in (4096, 8192, 16384):
         img = synth.rect_image(n, n, 3)
         px = n * n
@@ -129,7 +171,12 @@ def bench_sweep(torch, api, synth, dev, steps, warmup):
                 fn = lambda i: api.sobel4x5_u8(srcs[i % nsets], want_mag=False, dir_type=api.DIR_S16,
                                                dirs=outs[i % nsets])
             k = max(10, steps // (1 if n <= 8192 else 4))
-            ms = time_launches(torch, fn, k, max(3, warmup // 4))
+            if n <= 4096:
+                # shorter than a host call: graph replay
+                warm(torch, fn, max(3, warmup // 4))
+                ms = time_graph(torch, fn, min(nsets, 100), max(2, steps // 20))
+            else:
+                ms = time_launches(torch, fn, k, max(3, warmup // 4))
             gbs = per / (ms * 1e-3) / 1e9
             out["%d_%s" % (n, mode)] = {"ms": round(ms, 5), "gpx_per_s": round(px / (ms * 1e-3) / 1e9, 2),
                                         "alg_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
@@ -410,10 +457,24 @@ def cpu_baseline(img):
                 break
     except OSError:
         pass
+    # single-thread references: the 512x512 parity image with every output,
+    # and one 1024x1024 fp32 image forward + adjoint in fp64
+    from paper_2305_00515_amd import synth
+    small = synth.rect_image(512, 512, 0)
+    t0 = time.perf_counter()
+    oracle.sobel_u8(small, nthreads=1)
+    t_small = time.perf_counter() - t0
+    x = synth.float_batch(1, 1024, 1024).astype(np.float64)
+    t0 = time.perf_counter()
+    m, _ = oracle.sobel_f64_fwd(x, nthreads=1)
+    oracle.sobel_f64_bwd(x, np.full(m.shape, 1.0 / m.size), nthreads=1)
+    t_f64 = time.perf_counter() - t0
     return {"value": round(len(runs) * img.size / t_total / 1e9, 4), "unit": "Gpixel/s", "cores": cores,
             "kind": "oracle",
             "sample": "the full 8192x8192 uint8 image (magnitude only) repeated for >= 10 s: %d run(s), "
-                      "best %.3f s; CPU %s" % (len(runs), best, model)}
+                      "best %.3f s; CPU %s" % (len(runs), best, model),
+            "single_thread": {"u8_512x512_all_outputs_ms": round(t_small * 1e3, 2),
+                              "f64_1024x1024_fwd_bwd_ms": round(t_f64 * 1e3, 1)}}
 
 
 def main():
@@ -447,7 +508,7 @@ def main():
                                    "replicate border, one image per step",
                        "image": "rect_image(8192, 8192, seed=3): uniform noise + 20 filled rectangles",
                        "bytes_per_px": 2, "rotating_buffers_gib": round(r["rotating_gib"], 2),
-                       "hot_same_buffer_ms": round(r["hot_ms"], 5)},
+                       "hot_same_buffer_ms": round(r["hot_ms"], 5), "per_launch_us": r["per_launch_us"]},
             "roofline": {"bound": "alu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
                          "unit": "TOP/s", "frac": round(tops / VALU_PEAK_TOPS, 4),
                          "traffic": u8_traffic(),
