@@ -14,9 +14,12 @@
 // (every filter here is antisymmetric under a half turn), so on the padded
 // domain the adjoint is P = -(K_x * w_x + K_d- * w_m + K_y * w_y + K_d+ * w_p)
 // (* = correlation) of the weighted planes w = g dM/dG, zero where no output
-// pixel is centred.  The same factoring evaluates it.  The replicate border
-// then folds P at the two virtual rows and columns beyond each edge onto
-// that edge.
+// pixel is centred.  Every factor pair is applied down the columns first;
+// the five column results then meet in one correlation across the columns
+// whose taps are the matching combinations of the five row filters, so the
+// adjoint needs only four lane shifts per row.  The replicate border then
+// folds P at the two virtual rows and columns beyond each edge onto that
+// edge.
 //
 // Layout of the work: a wave owns a strip of columns and a range of rows of
 // one image.  Each lane holds two adjacent columns and walks down the rows,
@@ -112,12 +115,6 @@ __device__ __forceinline__ void hcombine(F2 vr, F2 vs, F2 &C, F2 &Cd)
     C = comb_c(r.m2, r.m1, vr, r.p1, r.p2);
     Cd = comb_cd(r.m2, r.m1, vr, r.p1, r.p2, t.m2, vs, t.p2);
 }
-// Only the c_h part (the K_y structure).
-__device__ __forceinline__ F2 hcombine_c(F2 vr)
-{
-    const Nb r = neighbours(vr);
-    return comb_c(r.m2, r.m1, vr, r.p1, r.p2);
-}
 
 __device__ __forceinline__ float sum_sq(float Gx, float Gy, float Gp, float Gm)
 {
@@ -132,10 +129,15 @@ __device__ __forceinline__ float mag_of(float Gx, float Gy, float Gp, float Gm)
 }
 
 // g / M = g / sqrt(S) for S > 0, 0 for S = 0: the hardware reciprocal square
-// root (within 1 ulp) for normal S, the exact library route below 2^-100.
+// root (within 1 ulp).  Below 2^-100 (down to the denormals, which the
+// hardware operation does not take) S is first scaled by 2^100 and the
+// result by 2^50; both scalings are exact, so the 1 ulp bound holds for
+// every S > 0.
 __device__ __forceinline__ float scale_of(float g, float S)
 {
-    return S >= 0x1p-100f ? g * __builtin_amdgcn_rsqf(S) : (S > 0.f ? g / sqrtf(S) : 0.f);
+    const bool tiny = S < 0x1p-100f;
+    const float r = __builtin_amdgcn_rsqf(S * (tiny ? 0x1p+100f : 1.0f)) * (tiny ? 0x1p+50f : 1.0f);
+    return S > 0.f ? g * r : 0.f;
 }
 
 template <int P>
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_fwd(F32Args a, int 
 // ---------------------------------------------------------------- adjoint
 // Wave (image b, strip s, chunk k): grad_src columns [s*116, s*116+116), rows
 // [X0, X1).  Lane l holds input columns c = s*116 - 6 + 2l + {0, 1}.  Step t
-// loads input row r = X0 - 6 + t; the centre row q = r - 2 gets its weighted
+// loads input row r = r0 + t; the centre row q = r - 2 gets its weighted
 // planes w; the padded adjoint row p = r - 4 is complete and is folded /
 // stored.
 template <int OFF>
@@ -258,11 +260,14 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
     const char *src = reinterpret_cast<const char *>(a.src) + (int64_t)b * a.src_bstride;
     const char *gr = reinterpret_cast<const char *>(a.grad) + (int64_t)b * a.g_bstride;
     char *dst = reinterpret_cast<char *>(a.out) + (int64_t)b * a.out_bstride + (int64_t)(c < 0 ? 0 : c) * 4;
-    const int r0 = X0 - 6;
-    const int T = X1 - X0 + 12;
     // replicate border: fold the virtual columns -2, -1 onto 0 and W, W+1
     // onto W-1 (wave-uniform: does this strip hold column 0 / W-1?)
     const bool rep = OFF == 0;
+    // input rows X0-4 .. X1+3 give the adjoint rows [X0, X1); at the top and
+    // bottom of the image under the replicate border two more rows on that
+    // side give the padded rows -2, -1 and H, H+1 that fold onto 0 and H-1
+    const int r0 = X0 - ((rep && X0 == 0) ? 6 : 4);
+    const int T = X1 + ((rep && X1 == a.H) ? 6 : 4) - r0;
     const bool fold_l = rep && s == 0;
     const bool fold_r = rep && s * kOwnB + kOwnB >= a.W;
 
@@ -281,13 +286,13 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
         return F2{oc_a ? v.a : 0.f, oc_b ? v.b : 0.f};
     };
 
-    // rings (slot = step mod 5): input rows, their row filters, centre-row
-    // planes w_y, w_p, and the row filters of w_x, w_m
-    F2 X[5], HR[5], HS[5], WY[5], WP[5], AX[5], AM[5], AS[5];
+    // rings (slot = step mod 5): input rows, their row filters, and the
+    // centre-row planes -w_x, -w_m, -w_y, -w_p
+    F2 X[5], HR[5], HS[5], WX[5], WM[5], WY[5], WP[5];
     F2 pfx[5], pfg[5];
 #pragma unroll
     for (int i = 0; i < 5; ++i)
-        X[i] = HR[i] = HS[i] = WY[i] = WP[i] = AX[i] = AM[i] = AS[i] = pfx[i] = pfg[i] = F2{0.f, 0.f};
+        X[i] = HR[i] = HS[i] = WX[i] = WM[i] = WY[i] = WP[i] = pfx[i] = pfg[i] = F2{0.f, 0.f};
     constexpr int PD = 3;
     // prologue loads in row order (the loop's first steps consume them)
 #pragma unroll
@@ -327,27 +332,38 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
         F2 Gy, Gp;
         hcombine(vr, vs, Gy, Gp);
         const F2 gq = pfg[p];                    // grad of the output row centred on q
-        const F2 sc{scale_of(gq.a, sum_sq(Gx.a, Gy.a, Gp.a, Gm.a)), scale_of(gq.b, sum_sq(Gx.b, Gy.b, Gp.b, Gm.b))};
-        const F2 wx{sc.a * Gx.a, sc.b * Gx.b}, wy{sc.a * Gy.a, sc.b * Gy.b};
-        const F2 wp{0.5f * sc.a * Gp.a, 0.5f * sc.b * Gp.b}, wm{0.5f * sc.a * Gm.a, 0.5f * sc.b * Gm.b};
+        // the planes enter negated, so the sums below are P itself
+        const F2 sc{-scale_of(gq.a, sum_sq(Gx.a, Gy.a, Gp.a, Gm.a)), -scale_of(gq.b, sum_sq(Gx.b, Gy.b, Gp.b, Gm.b))};
+        const F2 hsc = 0.5f * sc;
         // w rings hold centre rows q-4 .. q in slots (p+1)%5 .. p as well
-        WY[s4] = wy;
-        WP[s4] = wp;
-        F2 hs_x;   // (only h_r of w_x enters K_x)
-        hfilters(wx, AX[s4], hs_x);
-        hfilters(wm, AM[s4], AS[s4]);
-        // padded adjoint row p_ = q - 2 (slot s2 of the w rings):
-        // K_x * w_x + K_d- * w_m (rows first) + K_y * w_y + K_d+ * w_p (columns first)
-        const F2 A = comb_c(AX[s0], AX[s1], AX[s2], AX[s3], AX[s4]) +
-                     comb_cd(AM[s0], AM[s1], AM[s2], AM[s3], AM[s4], AS[s0], AS[s2], AS[s4]);
-        const F2 vsy = WY[s3] - WY[s1];
-        const F2 vry = (WY[s4] - WY[s0]) + 2.0f * vsy;
-        const F2 vsp = WP[s3] - WP[s1];
-        const F2 vrp = (WP[s4] - WP[s0]) + 2.0f * vsp;
-        const F2 By = hcombine_c(vry);
-        F2 Bp_c, Bp;
-        hcombine(vrp, vsp, Bp_c, Bp);
-        const F2 P = F2{0.f, 0.f} - (A + By + Bp);
+        WX[s4] = F2{sc.a * Gx.a, sc.b * Gx.b};
+        WY[s4] = F2{sc.a * Gy.a, sc.b * Gy.b};
+        WP[s4] = F2{hsc.a * Gp.a, hsc.b * Gp.b};
+        WM[s4] = F2{hsc.a * Gm.a, hsc.b * Gm.b};
+        // padded adjoint row p_ = q - 2 (slot s2 of the w rings).  Each term
+        // K = u_v (x) u_h is applied down the columns first:
+        //   V1 = c_v(w_x) + c'_v(w_m)  (row filter r),   V2 = d_v(w_m)  (-s),
+        //   V3 = r_v(w_y)              (row filter c),   V4 = r_v(w_p)  (c'),
+        //   V5 = s_v(w_p)              (-d),
+        // and then by one correlation across the columns whose tap dx takes
+        // Q_dx = r[dx] V1 - s[dx] V2 + c[dx] V3 + c'[dx] V4 - d[dx] V5.
+        const F2 e04m = WM[s0] + WM[s4];
+        const F2 V1 = comb_c(WX[s0], WX[s1], WX[s2], WX[s3], WX[s4]) +
+                      (6.0f * (e04m + (WM[s1] + WM[s3])) + 2.0f * WM[s2]);
+        const F2 V2 = 10.0f * e04m - 12.0f * WM[s2];
+        const F2 V3 = (WY[s4] - WY[s0]) + 2.0f * (WY[s3] - WY[s1]);
+        const F2 V5 = WP[s3] - WP[s1];
+        const F2 V4 = (WP[s4] - WP[s0]) + 2.0f * V5;
+        // Q_+-2 = E +- V1, Q_+-1 = F +- O, Q_0
+        const F2 E = V3 + 6.0f * V4 - 10.0f * V5;
+        const F2 Fq = 4.0f * V3 + 6.0f * V4;
+        const F2 O = 2.0f * V1 - V2;
+        const F2 Qm2 = E - V1, Qp2 = E + V1, Qm1 = Fq - O, Qp1 = Fq + O;
+        const F2 Q0 = 6.0f * V3 + 2.0f * V4 + 12.0f * V5;
+        // column a takes Q_-2, Q_-1 from the left lane's a, b, Q_+1 from its
+        // own b and Q_+2 from the right lane's a; column b likewise
+        const F2 P{(Q0.a + Qp1.b) + from_left(Qm2.a + Qm1.b) + from_right(Qp2.a),
+                   (Qm1.a + Q0.b) + from_left(Qm2.b) + from_right(Qp1.a + Qp2.b)};
         const int pr = r0 + t - 4;               // padded row of P
         if (pr < X0 - 2 || pr >= X1 + 2) return;  // warm-up and rows of other waves
         if (!rep) {
@@ -389,14 +405,15 @@ int resident_f32(const void *fn)
     return w;
 }
 
-// Row chunks per strip so that the grid is about one round of resident waves
-// (at least 32 rows per chunk: the pipeline costs 4 (forward) or 12 (adjoint)
-// extra row steps per chunk).
+// Row chunks per strip so that the grid fills at most one round of resident
+// waves (rounding up would leave a few waves to run as a second, nearly
+// empty round), with at least 32 rows per chunk: the pipeline costs 4
+// (forward) or 12 (adjoint) extra row steps per chunk.
 int chunks_for(const void *fn, int64_t strips, int rows)
 {
     int slots = resident_f32(fn);
     if (slots <= 0) slots = 4096;
-    int64_t n = (slots + strips - 1) / strips;
+    int64_t n = slots / strips;
     n = std::max<int64_t>(1, std::min<int64_t>(n, rows / 32));
     return (int)n;
 }

@@ -232,8 +232,9 @@ hipError_t launch_u8_weighted(const WJob &j, hipStream_t st)
     int nstrip = (j.Wo + kColsW - 1) / kColsW;
     int slots = resident_w(fn);
     if (slots <= 0) slots = 4096;
-    // about one round of resident waves, at least 16 rows per chunk
-    int nchunk = std::max(1, std::min((slots + nstrip - 1) / nstrip, std::max(1, j.Ho / 16)));
+    // at most one round of resident waves (rounding up would leave a few
+    // waves for a second, nearly empty round), at least 16 rows per chunk
+    int nchunk = std::max(1, std::min(slots / nstrip, std::max(1, j.Ho / 16)));
     const int64_t waves = (int64_t)nstrip * nchunk;
     const int grid = (int)((waves + kWavesW - 1) / kWavesW);
     WJob jj = j;

@@ -70,6 +70,24 @@ def test_noninteger_inputs(oracle_mod, sobel_lib, gpu):
     check_bwd(oracle_mod, x, g, dx.cpu().numpy(), 0)
 
 
+def test_tiny_magnitudes(oracle_mod, sobel_lib, gpu):
+    """Images scaled by 2^-50 (exact) put S = M^2 between about 2^-116 and
+    2^-84, on both sides of 2^-100 where the adjoint's reciprocal square root
+    switches to its scaled form; every S stays a normal fp32 number."""
+    x = f32_batch(2, 40, 70, 31) * np.float32(2.0 ** -50)
+    xt = torch.from_numpy(x).to(gpu)
+    M = sobel_lib.sobel4x5_f32_fwd(xt)
+    torch.cuda.synchronize()
+    Mh = M.cpu().numpy().astype(np.float64)
+    check_fwd(oracle_mod, x, Mh.astype(np.float32), 0)
+    S = Mh[Mh > 0] ** 2
+    assert S.min() < 2.0 ** -100 < S.max()
+    g = np.random.default_rng(4).standard_normal(M.shape).astype(np.float32)
+    dx = sobel_lib.sobel4x5_f32_bwd(xt, torch.from_numpy(g).to(gpu))
+    torch.cuda.synchronize()
+    check_bwd(oracle_mod, x, g, dx.cpu().numpy(), 0)
+
+
 def test_autograd_function(oracle_mod, sobel_lib, gpu):
     from paper_2305_00515_amd import sobel4x5_magnitude
     x = f32_batch(2, 48, 40, 5)
