@@ -23,16 +23,16 @@
  *     the pixels in Sec. 4.3);
  *   - border REPLICATE (clamp-to-edge) keeps the output at HxW; border VALID
  *     is the paper-native shrink by 2r = 4 rows and columns (Sec. 4.3, data
- *     flow), out(y, x) = full(y + 2, x + 2); the uint8 path also offers ZERO
- *     (pixels outside read 0) and REFLECT101 (mirror about the edge pixel,
- *     see border_index), both H x W;
+ *     flow), out(y, x) = full(y + 2, x + 2); ZERO (pixels outside read 0)
+ *     and REFLECT101 (mirror about the edge pixel, see border_index) keep
+ *     H x W as well;
  *   - the uint8 magnitude is min(255, round-to-nearest(sqrt(S))), computed
  *     exactly in integers (ties cannot occur for integer S);
  *   - the real-valued path (not in the paper) is the same correlation in fp64,
  *     summed as differences of opposite taps (see responses_f64), with
  *     M = sqrt(S); its adjoint is the literal scatter of every tap
- *     through the same clamped index, with the subgradient u_k = 0 where
- *     M = 0.
+ *     through the same border index (a tap that reads 0 under ZERO
+ *     scatters nothing), with the subgradient u_k = 0 where M = 0.
  *
  * Every loop below is the plain definition: no separable factoring, no
  * blocking, no reordering beyond pairing opposite taps in the real-valued
@@ -155,8 +155,7 @@ static int64_t round_sqrt_i64(int64_t S)
 
 int64_t oracle_round_sqrt(int64_t S) { return S < 0 ? -1 : round_sqrt_i64(S); }
 
-/* Output size under a border rule (the real-valued path takes REPLICATE and
- * VALID only). */
+/* Output size under a border rule. */
 static int out_dims(int W, int H, int border, int *Wo, int *Ho)
 {
     if (W <= 0 || H <= 0)
@@ -279,6 +278,14 @@ int oracle_u8_points(const uint8_t *src, int W, int H, long pitch, int border,
  * a spurious unit gradient direction G/M).  A weight table that is not
  * antisymmetric falls back to the direct sum term by term.
  */
+/* Real-valued pixel at (y, x) under the border rule (0 where ZERO reads
+ * outside the image). */
+static inline double pixel_f64(const double *x, int W, int H, int border, long y, long xx)
+{
+    const long yy = border_index(y, H, border), xi = border_index(xx, W, border);
+    return (yy < 0 || xi < 0) ? 0.0 : x[yy * W + xi];
+}
+
 static void responses_f64(const double *x, int W, int H, int border,
                           const int32_t *K, long yo, long xo, double G[4])
 {
@@ -293,14 +300,14 @@ static void responses_f64(const double *x, int W, int H, int border,
         for (int t = 0; t < 12; ++t) {
             int i = t / 5, j = t % 5;
             int ii = 4 - i, jj = 4 - j;
-            double a = x[clampl(yc + i - 2, 0, H - 1) * W + clampl(xc + j - 2, 0, W - 1)];
-            double b = x[clampl(yc + ii - 2, 0, H - 1) * W + clampl(xc + jj - 2, 0, W - 1)];
+            double a = pixel_f64(x, W, H, border, yc + i - 2, xc + j - 2);
+            double b = pixel_f64(x, W, H, border, yc + ii - 2, xc + jj - 2);
             if (Kk[ii * 5 + jj] == -Kk[i * 5 + j])
                 acc += (double)Kk[i * 5 + j] * (a - b);
             else
                 acc += (double)Kk[i * 5 + j] * a + (double)Kk[ii * 5 + jj] * b;
         }
-        acc += (double)Kk[12] * x[clampl(yc, 0, H - 1) * W + clampl(xc, 0, W - 1)];
+        acc += (double)Kk[12] * pixel_f64(x, W, H, border, yc, xc);
         G[k] = acc;
     }
 }
@@ -311,7 +318,7 @@ int oracle_f64_fwd(const double *x, int B, int H, int W, int border,
                    double *mag, double *dir, const int32_t *weights, int nthreads)
 {
     int Wo, Ho;
-    if (!x || B < 0 || border > OR_BORDER_VALID || out_dims(W, H, border, &Wo, &Ho) != OR_OK)
+    if (!x || B < 0 || out_dims(W, H, border, &Wo, &Ho) != OR_OK)
         return OR_EINVAL;
     const int32_t *K = pick_weights(weights);
     const long plane_in = (long)W * H, plane_out = (long)Wo * Ho;
@@ -348,7 +355,7 @@ static int bwd_impl(const double *x, const double *g, int B, int H, int W, int b
                     double *dx, const int32_t *weights, int nthreads, int absmode)
 {
     int Wo, Ho;
-    if (!x || !g || !dx || B < 0 || border > OR_BORDER_VALID || out_dims(W, H, border, &Wo, &Ho) != OR_OK)
+    if (!x || !g || !dx || B < 0 || out_dims(W, H, border, &Wo, &Ho) != OR_OK)
         return OR_EINVAL;
     const int32_t *K = pick_weights(weights);
     const long plane_in = (long)W * H, plane_out = (long)Wo * Ho;
@@ -376,9 +383,11 @@ static int bwd_impl(const double *x, const double *g, int B, int H, int W, int b
                     if (absmode)
                         u = fabs(u);
                     for (int i = 0; i < 5; ++i) {
-                        long yy = clampl(yc + i - 2, 0, H - 1);
+                        long yy = border_index(yc + i - 2, H, border);
                         for (int j = 0; j < 5; ++j) {
-                            long xx = clampl(xc + j - 2, 0, W - 1);
+                            long xx = border_index(xc + j - 2, W, border);
+                            if (yy < 0 || xx < 0)
+                                continue;   /* ZERO: the tap read a constant */
                             double w = (double)K[(k * 5 + i) * 5 + j];
                             db[yy * W + xx] += (absmode ? fabs(w) : w) * u;
                         }
@@ -410,7 +419,7 @@ int oracle_f64_fwd_scale(const double *x, int B, int H, int W, int border, doubl
                          const int32_t *weights, int nthreads)
 {
     int Wo, Ho;
-    if (!x || !scale || B < 0 || border > OR_BORDER_VALID || out_dims(W, H, border, &Wo, &Ho) != OR_OK)
+    if (!x || !scale || B < 0 || out_dims(W, H, border, &Wo, &Ho) != OR_OK)
         return OR_EINVAL;
     const int32_t *K = pick_weights(weights);
     const long plane_in = (long)W * H, plane_out = (long)Wo * Ho;
@@ -426,13 +435,10 @@ int oracle_f64_fwd_scale(const double *x, int B, int H, int W, int border, doubl
                 double best = 0.0;
                 for (int k = 0; k < 4; ++k) {
                     double acc = 0.0;
-                    for (int i = 0; i < 5; ++i) {
-                        long yy = clampl(yc + i - 2, 0, H - 1);
-                        for (int j = 0; j < 5; ++j) {
-                            long xx = clampl(xc + j - 2, 0, W - 1);
-                            acc += fabs((double)K[(k * 5 + i) * 5 + j] * x[b * plane_in + yy * W + xx]);
-                        }
-                    }
+                    for (int i = 0; i < 5; ++i)
+                        for (int j = 0; j < 5; ++j)
+                            acc += fabs((double)K[(k * 5 + i) * 5 + j] *
+                                        pixel_f64(x + b * plane_in, W, H, border, yc + i - 2, xc + j - 2));
                     if (acc > best)
                         best = acc;
                 }

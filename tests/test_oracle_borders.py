@@ -121,8 +121,34 @@ def test_planted_mistake_reflect_with_edge_repeat(oracle_mod):
     assert not np.array_equal(d[0], wrong)
 
 
-def test_real_valued_path_rejects_the_new_borders(oracle_mod):
-    x = np.zeros((1, 8, 8))
-    for b in (ZERO, REFLECT101):
-        with pytest.raises(ValueError):
-            oracle_mod.sobel_f64_fwd(x, b)
+@pytest.mark.parametrize("border", [ZERO, REFLECT101])
+@pytest.mark.parametrize("h,w", [(1, 1), (2, 3), (3, 2), (4, 4), (9, 6), (33, 47)])
+def test_real_valued_path_equals_the_integer_path(oracle_mod, border, h, w):
+    """On integer images the fp64 responses are exact, so they equal the
+    integer path's under the same border rule bit for bit."""
+    img = synth.rect_image(h, w, 40 + h + w)
+    _, d = oracle_mod.sobel_u8(img, border)
+    M, D = oracle_mod.sobel_f64_fwd(img.astype(np.float64)[None], border, want_dir=True)
+    assert np.array_equal(D[0], d.astype(np.float64))
+    assert np.array_equal(M[0], np.sqrt((d.astype(np.float64) ** 2).sum(0)))
+
+
+def test_real_valued_adjoint_zero_border_drops_outside_taps(oracle_mod):
+    """Under ZERO the adjoint of one output pixel is the four filters cut
+    off at the image edge: with g = 1 at the corner pixel only, dx is
+    sum_k K_k[t] G_k / M over the in-image taps t and zero elsewhere."""
+    x = np.zeros((1, 6, 7))
+    x[0, 0, 2] = 1.0                     # an impulse two columns right of (0, 0)
+    M, D = oracle_mod.sobel_f64_fwd(x, ZERO, want_dir=True)
+    g = np.zeros_like(M)
+    g[0, 0, 0] = 1.0
+    dx = oracle_mod.sobel_f64_bwd(x, g, ZERO)
+    K = oracle_mod.weights().astype(np.float64)
+    G = D[0, :, 0, 0]
+    want = np.zeros((6, 7))
+    for k in range(4):
+        want[:3, :3] += K[k, 2:, 2:] * G[k] / M[0, 0, 0]
+    np.testing.assert_allclose(dx[0], want, rtol=1e-14, atol=1e-15)
+    # the replicate rule folds the outside taps onto the edge instead
+    dr = oracle_mod.sobel_f64_bwd(x, g, REPLICATE)
+    assert not np.allclose(dr, dx)

@@ -1,9 +1,11 @@
 """Pins for the oracle's real-valued path (forward magnitude and its adjoint).
 
-The forward is pinned to torch's conv2d after replicate padding (a library
-routine) and to the oracle's own integer path on integer images.  The adjoint
-is pinned to torch's reverse-mode autograd through that same library forward
-(fp64, safe square root) and to central finite differences.
+The forward is pinned to torch's conv2d after padding (a library routine:
+replicate, zero, or a reflect-101 gather whose indices come from numpy's
+'reflect' pad, which also covers images smaller than the pad) and to the
+oracle's own integer path on integer images.  The adjoint is pinned to
+torch's reverse-mode autograd through that same library forward (fp64, safe
+square root) and to central finite differences.
 """
 import numpy as np
 import pytest
@@ -15,10 +17,16 @@ import torch.nn.functional as F  # noqa: E402
 
 
 def torch_forward(x, K, border):
-    """Library forward: replicate pad + conv2d (a correlation) + safe sqrt."""
+    """Library forward: pad + conv2d (a correlation) + safe sqrt."""
     t = x[:, None]
     if border == 0:
         t = F.pad(t, (2, 2, 2, 2), mode="replicate")
+    elif border == 2:
+        t = F.pad(t, (2, 2, 2, 2), mode="constant", value=0.0)
+    elif border == 3:
+        ri = torch.from_numpy(np.pad(np.arange(x.shape[1]), 2, mode="reflect"))
+        ci = torch.from_numpy(np.pad(np.arange(x.shape[2]), 2, mode="reflect"))
+        t = t[:, :, ri][:, :, :, ci]
     wt = torch.from_numpy(K.astype(np.float64))[:, None]
     G = F.conv2d(t, wt)
     S = (G * G).sum(1)
@@ -27,7 +35,7 @@ def torch_forward(x, K, border):
     return torch.where(pos, torch.sqrt(safe), torch.zeros_like(S)), G
 
 
-@pytest.mark.parametrize("border", [0, 1])
+@pytest.mark.parametrize("border", [0, 1, 2, 3])
 def test_f64_forward_matches_torch(oracle_mod, border):
     rng = np.random.default_rng(1)
     x = rng.random((2, 19, 23))
@@ -58,8 +66,8 @@ def test_f64_values_k_over_255_are_exact(oracle_mod):
     assert np.array_equal(D * 2.0 ** 31, Di)
 
 
-@pytest.mark.parametrize("border", [0, 1])
-@pytest.mark.parametrize("shape", [(1, 9, 11), (2, 17, 13), (1, 5, 5), (1, 1, 7), (1, 3, 2)])
+@pytest.mark.parametrize("border", [0, 1, 2, 3])
+@pytest.mark.parametrize("shape", [(1, 9, 11), (2, 17, 13), (1, 5, 5), (1, 1, 7), (1, 3, 2), (1, 2, 4), (1, 4, 3)])
 def test_f64_backward_matches_torch_autograd(oracle_mod, border, shape):
     b, h, w = shape
     if border == 1 and (h < 5 or w < 5):
@@ -107,16 +115,17 @@ def test_f64_backward_central_differences(oracle_mod):
         assert abs(rich - dx[0, py, px]) <= 1e-7 * max(1.0, abs(dx[0, py, px])), (py, px)
 
 
-def test_error_scales_bound_the_results(oracle_mod):
+@pytest.mark.parametrize("border", [0, 1, 2, 3])
+def test_error_scales_bound_the_results(oracle_mod, border):
     """The tolerance scales dominate the quantities they scale."""
     rng = np.random.default_rng(4)
     x = rng.random((2, 14, 17))
-    M, D = oracle_mod.sobel_f64_fwd(x, want_dir=True)
-    sf = oracle_mod.sobel_f64_fwd_scale(x)
+    M, D = oracle_mod.sobel_f64_fwd(x, border, want_dir=True)
+    sf = oracle_mod.sobel_f64_fwd_scale(x, border)
     assert np.all(np.abs(D).max(axis=1) <= sf + 1e-12)
     g = rng.standard_normal(M.shape)
-    dx = oracle_mod.sobel_f64_bwd(x, g)
-    A = oracle_mod.sobel_f64_bwd_scale(x, g)
+    dx = oracle_mod.sobel_f64_bwd(x, g, border)
+    A = oracle_mod.sobel_f64_bwd_scale(x, g, border)
     assert np.all(np.abs(dx) <= A + 1e-12)
     assert np.all(A >= 0)
     # a constant image has no terms at all
