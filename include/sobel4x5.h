@@ -41,9 +41,8 @@
  *                               W+1 -> W-3); an axis of 1 or 2 pixels
  *                               reflects again until the index lands inside
  *                               (period 2(n-1)).  H x W; any H, W >= 1.
- *   ZERO and REFLECT101 serve the uint8 entry points (single, operators,
- *   run-time weights, batched, pipeline); the fp32 pair returns
- *   SOBEL4X5_EUNSUPPORTED for them.
+ *   Every entry point serves all four (uint8 single, operators, run-time
+ *   weights, batched, pipeline, and the fp32 pair).
  *
  * uint8 magnitude: min(255, round-to-nearest(sqrt(S))), S = Gx^2 + Gd^2 +
  * Gy^2 + Gdt^2 -- exact (integer S never sits on a half-way point).
@@ -57,7 +56,7 @@
 extern "C" {
 #endif
 
-#define SOBEL4X5_VERSION 110
+#define SOBEL4X5_VERSION 111
 
 /* status codes */
 #define SOBEL4X5_OK 0
@@ -295,9 +294,11 @@ int sobel4x5_f32_fwd(const float *src, int32_t batch, int32_t width, int32_t hei
  * sobel4x5_f32_bwd -- adjoint of sobel4x5_f32_fwd: given grad_mag = dL/dM
  * (Ho x Wo per image), writes grad_src = dL/dsrc (H x W per image,
  * overwritten).  u_k = grad_mag * G_k / M where M > 0 and 0 where M = 0; each
- * u_k is spread back through the transposed filter, and the contributions
- * that the replicate border sent to clamped pixels are folded onto the edge
- * rows and columns.  G is recomputed from src (no saved state).
+ * u_k is spread back through the transposed filter.  The contributions that
+ * fell on positions outside the image go to the pixel the border rule read
+ * there: the edge pixel (REPLICATE), the mirror pixel (REFLECT101), or
+ * nowhere (ZERO: those taps read a constant).  G is recomputed from src (no
+ * saved state).
  */
 int sobel4x5_f32_bwd(const float *src, int64_t src_pitch, int64_t src_bstride,
                      const float *grad_mag, int64_t g_pitch, int64_t g_bstride,

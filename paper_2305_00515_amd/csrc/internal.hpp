@@ -117,7 +117,8 @@ struct F32Args {
     const float *grad;                    // bwd only
     int64_t g_pitch, g_bstride;           // bytes
     int32_t B, W, H, Wo, Ho;
-    int32_t off;                          // 0 replicate, 2 valid
+    int32_t off;                          // 0 replicate / zero / reflect-101, 2 valid
+    int32_t bmode;                        // 0 clamp (replicate, valid), 1 zero, 2 reflect-101
 };
 
 hipError_t launch_f32_fwd(const F32Args &a, hipStream_t stream);

@@ -194,6 +194,13 @@ U8Shape default_shape(int32_t Wo, int32_t Ho, int32_t dir_type)
     return s;
 }
 
+// Border rule of the fp32 kernels: 0 reads the nearest pixel (REPLICATE,
+// and VALID, whose taps stay inside), 1 ZERO, 2 REFLECT101.
+int f32_bmode(int32_t border)
+{
+    return border == SOBEL4X5_BORDER_ZERO ? 1 : border == SOBEL4X5_BORDER_REFLECT101 ? 2 : 0;
+}
+
 // A batch of `batch` fp32 images of rows x cols, image b at p + b*bstride.
 int check_f32_buf(const char *name, const float *p, int32_t batch, int32_t cols, int32_t rows, int64_t pitch,
                   int64_t bstride, Range *r)
@@ -865,8 +872,6 @@ int sobel4x5_validate_f32(const float *src, int32_t batch, int32_t width, int32_
 {
     int32_t Wo, Ho;
     if (int rc = out_dims(width, height, border, &Wo, &Ho)) return rc;
-    if (border != SOBEL4X5_BORDER_REPLICATE && border != SOBEL4X5_BORDER_VALID)
-        return fail(SOBEL4X5_EUNSUPPORTED, "the fp32 path serves the REPLICATE and VALID borders only");
     if (batch < 0) return fail(SOBEL4X5_EINVAL, "batch must be >= 0");
     Range rs, ro;
     if (int rc = check_f32_buf("src", src, batch, width, height, src_pitch, src_bstride, &rs)) return rc;
@@ -894,6 +899,7 @@ int sobel4x5_f32_fwd(const float *src, int32_t batch, int32_t width, int32_t hei
     a.H = height;
     out_dims(width, height, border, &a.Wo, &a.Ho);
     a.off = border == SOBEL4X5_BORDER_VALID ? 2 : 0;
+    a.bmode = f32_bmode(border);
     hipError_t e = launch_f32_fwd(a, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_f32_fwd launch");
 }
@@ -904,8 +910,6 @@ int sobel4x5_f32_bwd(const float *src, int64_t src_pitch, int64_t src_bstride, c
 {
     int32_t Wo, Ho;
     if (int rc = out_dims(width, height, border, &Wo, &Ho)) return rc;
-    if (border != SOBEL4X5_BORDER_REPLICATE && border != SOBEL4X5_BORDER_VALID)
-        return fail(SOBEL4X5_EUNSUPPORTED, "the fp32 path serves the REPLICATE and VALID borders only");
     if (batch < 0) return fail(SOBEL4X5_EINVAL, "batch must be >= 0");
     Range rs, rg, rd;
     if (int rc = check_f32_buf("src", src, batch, width, height, src_pitch, src_bstride, &rs)) return rc;
@@ -929,6 +933,7 @@ int sobel4x5_f32_bwd(const float *src, int64_t src_pitch, int64_t src_bstride, c
     a.Wo = Wo;
     a.Ho = Ho;
     a.off = border == SOBEL4X5_BORDER_VALID ? 2 : 0;
+    a.bmode = f32_bmode(border);
     hipError_t e = launch_f32_bwd(a, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_f32_bwd launch");
 }

@@ -46,6 +46,27 @@ constexpr int kHaloB = 6, kOwnB = 128 - 2 * kHaloB;   // adjoint: 116 columns pe
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Border rules of the real-valued path (VALID reads like CLAMP: its taps
+// never leave the image).
+constexpr int kClamp = 0, kZero = 1, kRefl = 2;
+
+// Index that stands in for position i of an axis of n pixels (0 <= i < n
+// maps to itself): the nearest pixel, except under REFLECT101, which mirrors
+// about the edge pixel without repeating it, again and again until the index
+// lands inside (n = 1 gives 0).  ZERO takes the nearest pixel as a safe
+// address and masks the value.
+template <int BM>
+__device__ __forceinline__ int edge_index(int i, int n)
+{
+    if constexpr (BM == kRefl) {
+        if (n == 1) return 0;
+        while (i < 0 || i >= n) i = i < 0 ? -i : 2 * (n - 1) - i;
+        return i;
+    } else {
+        return clampi(i, 0, n - 1);
+    }
+}
+
 // value held by lane + 1 / lane - 1 (wave-wide DPP shift; bound_ctrl gives
 // the last / first lane 0, which no kept column uses, and lets the move
 // write its destination without first clearing it)
@@ -175,8 +196,8 @@ __device__ __forceinline__ void run_steps(int T, Step &step)
 // Wave (image b, strip s, chunk k): output columns [s*124, s*124+124),
 // output rows [o0, o1).  Lane l holds output columns s*124 - 2 + 2l + {0, 1}
 // (centre columns + OFF).  Step t loads input row o0 + OFF - 2 + t and, from
-// t = 4 on, finishes output row o0 + t - 4.
-template <int OFF>
+// t = 4 on, finishes output row o0 + t - 4.  BM is the border rule.
+template <int OFF, int BM>
 __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_fwd(F32Args a, int nstrip, int nchunk)
 {
     const int wave = blockIdx.x * kWavesPerGroup + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -191,13 +212,21 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_fwd(F32Args a, int 
     const bool in_lane = lane >= kHaloF / 2 && lane < (kHaloF + kOwnF) / 2;
     const bool keep_a = in_lane && ox < a.Wo, keep_b = in_lane && ox + 1 < a.Wo;
     const char *src = reinterpret_cast<const char *>(a.src) + (int64_t)b * a.src_bstride;
-    const int64_t xa = (int64_t)clampi(ox + OFF, 0, a.W - 1) * 4, xb = (int64_t)clampi(ox + 1 + OFF, 0, a.W - 1) * 4;
+    const int64_t xa = (int64_t)edge_index<BM>(ox + OFF, a.W) * 4, xb = (int64_t)edge_index<BM>(ox + 1 + OFF, a.W) * 4;
+    // ZERO: does the lane's column lie inside the image?
+    const bool ina = ox + OFF >= 0 && ox + OFF < a.W, inb = ox + 1 + OFF >= 0 && ox + 1 + OFF < a.W;
     char *dst = reinterpret_cast<char *>(a.out) + (int64_t)b * a.out_bstride;
     const int64_t oa = (int64_t)(ox < 0 ? 0 : ox) * 4;
     const int r0 = o0 + OFF - 2;
     auto ld = [&](int t) {
-        const char *row = src + (int64_t)clampi(r0 + t, 0, a.H - 1) * a.src_pitch;
-        return F2{*reinterpret_cast<const float *>(row + xa), *reinterpret_cast<const float *>(row + xb)};
+        const int r = r0 + t;
+        const char *row = src + (int64_t)edge_index<BM>(r, a.H) * a.src_pitch;
+        F2 v{*reinterpret_cast<const float *>(row + xa), *reinterpret_cast<const float *>(row + xb)};
+        if constexpr (BM == kZero) {
+            const bool rin = r >= 0 && r < a.H;
+            v = F2{rin && ina ? v.a : 0.f, rin && inb ? v.b : 0.f};
+        }
+        return v;
     };
     const int T = o1 - o0 + 4;
 
@@ -238,8 +267,10 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_fwd(F32Args a, int 
 // [X0, X1).  Lane l holds input columns c = s*116 - 6 + 2l + {0, 1}.  Step t
 // loads input row r = r0 + t; the centre row q = r - 2 gets its weighted
 // planes w; the padded adjoint row p = r - 4 is complete and is folded /
-// stored.
-template <int OFF>
+// stored.  BM is the border rule: under REPLICATE and REFLECT101 the padded
+// rows and columns -2, -1, H, H+1 (W, W+1) fold back onto the pixels that
+// stood in for them; under ZERO and VALID they are dropped.
+template <int OFF, int BM>
 __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int nstrip, int nchunk)
 {
     const int wave = blockIdx.x * kWavesPerGroup + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -255,25 +286,35 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
     const bool keep_a = in_lane && c < a.W, keep_b = in_lane && c + 1 < a.W;
     // an output pixel is centred on the column
     const bool oc_a = c - OFF >= 0 && c - OFF < a.Wo, oc_b = c + 1 - OFF >= 0 && c + 1 - OFF < a.Wo;
-    const int64_t xa = (int64_t)clampi(c, 0, a.W - 1) * 4, xb = (int64_t)clampi(c + 1, 0, a.W - 1) * 4;
+    const int64_t xa = (int64_t)edge_index<BM>(c, a.W) * 4, xb = (int64_t)edge_index<BM>(c + 1, a.W) * 4;
+    const bool ina = c >= 0 && c < a.W, inb = c + 1 >= 0 && c + 1 < a.W;   // (ZERO)
     const int64_t ga = (int64_t)clampi(c - OFF, 0, a.Wo - 1) * 4, gb = (int64_t)clampi(c + 1 - OFF, 0, a.Wo - 1) * 4;
     const char *src = reinterpret_cast<const char *>(a.src) + (int64_t)b * a.src_bstride;
     const char *gr = reinterpret_cast<const char *>(a.grad) + (int64_t)b * a.g_bstride;
     char *dst = reinterpret_cast<char *>(a.out) + (int64_t)b * a.out_bstride + (int64_t)(c < 0 ? 0 : c) * 4;
-    // replicate border: fold the virtual columns -2, -1 onto 0 and W, W+1
-    // onto W-1 (wave-uniform: does this strip hold column 0 / W-1?)
-    const bool rep = OFF == 0;
+    // replicate: fold the padded columns -2, -1 onto 0 and W, W+1 onto W-1;
+    // reflect-101: -1, -2 onto 1, 2 and W, W+1 onto W-2, W-3 (as the
+    // index rule maps them for narrow images).  Wave-uniform: does this
+    // strip hold column 0 / W-1?
+    constexpr bool kFold = OFF == 0 && BM != kZero;
+    const bool fold_l = kFold && s == 0;
+    const bool fold_r = kFold && s * kOwnB + kOwnB >= a.W;
+    const int c0 = s * kOwnB - kHaloB;                        // column of lane 0's element a
     // input rows X0-4 .. X1+3 give the adjoint rows [X0, X1); at the top and
-    // bottom of the image under the replicate border two more rows on that
-    // side give the padded rows -2, -1 and H, H+1 that fold onto 0 and H-1
-    const int r0 = X0 - ((rep && X0 == 0) ? 6 : 4);
-    const int T = X1 + ((rep && X1 == a.H) ? 6 : 4) - r0;
-    const bool fold_l = rep && s == 0;
-    const bool fold_r = rep && s * kOwnB + kOwnB >= a.W;
+    // bottom of the image, where padded rows fold back, two more rows on
+    // that side give the padded rows -2, -1 and H, H+1
+    const int r0 = X0 - ((kFold && X0 == 0) ? 6 : 4);
+    const int T = X1 + ((kFold && X1 == a.H) ? 6 : 4) - r0;
 
     auto ldx = [&](int t) {
-        const char *row = src + (int64_t)clampi(r0 + t, 0, a.H - 1) * a.src_pitch;
-        return F2{*reinterpret_cast<const float *>(row + xa), *reinterpret_cast<const float *>(row + xb)};
+        const int r = r0 + t;
+        const char *row = src + (int64_t)edge_index<BM>(r, a.H) * a.src_pitch;
+        F2 v{*reinterpret_cast<const float *>(row + xa), *reinterpret_cast<const float *>(row + xb)};
+        if constexpr (BM == kZero) {
+            const bool rin = r >= 0 && r < a.H;
+            v = F2{rin && ina ? v.a : 0.f, rin && inb ? v.b : 0.f};
+        }
+        return v;
     };
     // grad of the output row whose centre is input row r0 + t - 2 (0 outside)
     auto ldg = [&](int t) {
@@ -301,21 +342,55 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
         pfg[t] = ldg(t);
         __builtin_amdgcn_sched_barrier(0);
     }
+    // replicate: sums of the padded rows above row 0 / from row H-1 down;
+    // reflect-101: padded rows -2, -1, and the last three rows, held until
+    // the padded rows H, H+1 have been added
     F2 acc_top{0.f, 0.f}, acc_bot{0.f, 0.f};
+    F2 top2{0.f, 0.f}, top1{0.f, 0.f}, hold0{0.f, 0.f}, hold1{0.f, 0.f}, hold2{0.f, 0.f};
 
-    auto store = [&](int row, F2 v) {
-        if (fold_l || fold_r) {
-            const Nb n = neighbours(v);   // from the row-folded values of every lane
-            if (fold_l && c == 0) v.a += n.m2.a + n.m1.a;                  // columns -2, -1
-            if (fold_r && c == a.W - 1) v.a += n.p1.a + n.p2.a;            // columns W, W+1
-            if (fold_r && c + 1 == a.W - 1) v.b += n.p1.b + n.p2.b;
+    auto store = [&](int row, F2 v) __attribute__((always_inline)) {
+        if constexpr (kFold && BM == kClamp) {
+            if (fold_l || fold_r) {
+                const Nb n = neighbours(v);   // from the row-folded values of every lane
+                if (fold_l && c == 0) v.a += n.m2.a + n.m1.a;                  // columns -2, -1
+                if (fold_r && c == a.W - 1) v.a += n.p1.a + n.p2.a;            // columns W, W+1
+                if (fold_r && c + 1 == a.W - 1) v.b += n.p1.b + n.p2.b;
+            }
+        }
+        if constexpr (kFold && BM == kRefl) {
+            if (fold_l || fold_r) {
+                // a padded column vc sits in lane (vc - c0) / 2 (lanes 2 .. 61),
+                // element (vc - c0) & 1: read it there, add it at its mirror
+                auto at = [&](int vc) __attribute__((always_inline)) {
+                    const int d = vc - c0;
+                    const int ea = __builtin_amdgcn_readlane(__builtin_bit_cast(int, v.a), d >> 1);
+                    const int eb = __builtin_amdgcn_readlane(__builtin_bit_cast(int, v.b), d >> 1);
+                    return __builtin_bit_cast(float, (d & 1) ? eb : ea);
+                };
+                auto add_at = [&](int vc, float pv) __attribute__((always_inline)) {
+                    const int tc = edge_index<kRefl>(vc, a.W);
+                    if (c == tc) v.a += pv;
+                    if (c + 1 == tc) v.b += pv;
+                };
+                // (targets lie inside the image, so no read sees an earlier add)
+                if (fold_l) {
+                    const float m2 = at(-2), m1 = at(-1);
+                    add_at(-2, m2);
+                    add_at(-1, m1);
+                }
+                if (fold_r) {
+                    const float p0 = at(a.W), p1 = at(a.W + 1);
+                    add_at(a.W, p0);
+                    add_at(a.W + 1, p1);
+                }
+            }
         }
         float *p = reinterpret_cast<float *>(dst + (int64_t)row * a.out_pitch);
         if (keep_a) p[0] = v.a;
         if (keep_b) p[1] = v.b;
     };
 
-    auto step = [&](int t, auto phase) {
+    auto step = [&](int t, auto phase) __attribute__((always_inline)) {
         constexpr int p = decltype(phase)::value;
         // input rows t-4 .. t live in slots (p+1)%5 .. p
         constexpr int s0 = (p + 1) % 5, s1 = (p + 2) % 5, s2 = (p + 3) % 5, s3 = (p + 4) % 5, s4 = p;
@@ -366,8 +441,48 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
                    (Qm1.a + Q0.b) + from_left(Qm2.b) + from_right(Qp1.a + Qp2.b)};
         const int pr = r0 + t - 4;               // padded row of P
         if (pr < X0 - 2 || pr >= X1 + 2) return;  // warm-up and rows of other waves
-        if (!rep) {
+        if constexpr (!kFold) {                   // VALID, ZERO: nothing folds back
             if (pr >= X0 && pr < X1) store(pr, P);
+            return;
+        }
+        if constexpr (BM == kRefl) {
+            // the last rows of the image, [H-3, H), are held: hold<k> is row
+            // H-3+k (k is wave-uniform; selects, not an indexed array, keep
+            // them in registers)
+            if (pr < 0) {                          // padded rows -2, -1 (top chunk)
+                if (pr == -2)
+                    top2 = P;
+                else
+                    top1 = P;
+                return;
+            }
+            if (pr >= a.H) {                       // padded rows H, H+1 (bottom chunk)
+                const int k = edge_index<kRefl>(pr, a.H) - (a.H - 3);
+                if (k == 0)
+                    hold0 = hold0 + P;
+                else if (k == 1)
+                    hold1 = hold1 + P;
+                else
+                    hold2 = hold2 + P;
+                return;                            // stored after the last step
+            }
+            if (pr < X0 || pr >= X1) return;
+            F2 v = P;
+            if (X0 == 0) {
+                if (edge_index<kRefl>(-1, a.H) == pr) v = v + top1;
+                if (edge_index<kRefl>(-2, a.H) == pr) v = v + top2;
+            }
+            if (X1 == a.H && pr >= a.H - 3) {
+                const int k = pr - (a.H - 3);
+                if (k == 0)
+                    hold0 = v;
+                else if (k == 1)
+                    hold1 = v;
+                else
+                    hold2 = v;
+            } else {
+                store(pr, v);
+            }
             return;
         }
         if (pr < 0) {
@@ -385,6 +500,13 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
         }
     };
     run_steps(T, step);
+    if constexpr (kFold && BM == kRefl) {
+        if (X1 == a.H) {                           // the held rows, with H and H+1 added
+            if (a.H - 3 >= X0) store(a.H - 3, hold0);
+            if (a.H - 2 >= X0) store(a.H - 2, hold1);
+            store(a.H - 1, hold2);
+        }
+    }
 }
 
 // Resident waves of a kernel (cached per kernel).
@@ -423,7 +545,10 @@ int chunks_for(const void *fn, int64_t strips, int rows)
 hipError_t launch_f32_fwd(const F32Args &a, hipStream_t st)
 {
     if (a.B <= 0 || a.Ho <= 0 || a.Wo <= 0) return hipSuccess;
-    const void *fn = a.off ? reinterpret_cast<const void *>(&k_f32_fwd<2>) : reinterpret_cast<const void *>(&k_f32_fwd<0>);
+    const void *fn = a.off ? reinterpret_cast<const void *>(&k_f32_fwd<2, kClamp>)
+                   : a.bmode == 1 ? reinterpret_cast<const void *>(&k_f32_fwd<0, kZero>)
+                   : a.bmode == 2 ? reinterpret_cast<const void *>(&k_f32_fwd<0, kRefl>)
+                                  : reinterpret_cast<const void *>(&k_f32_fwd<0, kClamp>);
     int nstrip = (a.Wo + kOwnF - 1) / kOwnF;
     int nchunk = chunks_for(fn, (int64_t)a.B * nstrip, a.Ho);
     const int64_t waves = (int64_t)a.B * nstrip * nchunk;
@@ -436,7 +561,10 @@ hipError_t launch_f32_fwd(const F32Args &a, hipStream_t st)
 hipError_t launch_f32_bwd(const F32Args &a, hipStream_t st)
 {
     if (a.B <= 0) return hipSuccess;
-    const void *fn = a.off ? reinterpret_cast<const void *>(&k_f32_bwd<2>) : reinterpret_cast<const void *>(&k_f32_bwd<0>);
+    const void *fn = a.off ? reinterpret_cast<const void *>(&k_f32_bwd<2, kClamp>)
+                   : a.bmode == 1 ? reinterpret_cast<const void *>(&k_f32_bwd<0, kZero>)
+                   : a.bmode == 2 ? reinterpret_cast<const void *>(&k_f32_bwd<0, kRefl>)
+                                  : reinterpret_cast<const void *>(&k_f32_bwd<0, kClamp>);
     int nstrip = (a.W + kOwnB - 1) / kOwnB;
     int nchunk = chunks_for(fn, (int64_t)a.B * nstrip, a.H);
     const int64_t waves = (int64_t)a.B * nstrip * nchunk;

@@ -185,8 +185,10 @@ def test_validate_f32(sobel_lib):
     assert f(src, 2, 64, 32, 256, 256 * 32, 0, src + 64, 256, 256 * 32) == api.EINVAL  # overlap
     assert f(src, 1, 4, 4, 16, 0, 1, out, 16, 0) == api.EINVAL                     # VALID < 5
     assert f(src, 0, 8, 8, 32, 0, 0, out, 32, 0) == 0                               # empty batch
-    for b in (2, 3):                                                                  # uint8 path only
-        assert f(src, 2, 64, 32, 256, 256 * 32, b, out, 256, 256 * 32) == api.EUNSUPPORTED
+    for b in (2, 3):                                                                  # ZERO, REFLECT101
+        assert f(src, 2, 64, 32, 256, 256 * 32, b, out, 256, 256 * 32) == 0
+        assert f(src, 1, 1, 1, 4, 0, b, out, 4, 0) == 0                              # any H, W >= 1
+    assert f(src, 2, 64, 32, 256, 256 * 32, 4, out, 256, 256 * 32) == api.EINVAL     # no such rule
 
 
 def test_plan_handles_are_checked(sobel_lib):

@@ -39,9 +39,13 @@ def check_bwd(oracle_mod, x, g, dx, border):
     assert np.linalg.norm(err) <= TOL * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("border", [0, 1])
-@pytest.mark.parametrize("shape", [(1, 5, 5), (2, 37, 45), (1, 64, 64), (3, 100, 33), (1, 1, 9), (1, 7, 1)])
+@pytest.mark.parametrize("border", [0, 1, 2, 3])
+@pytest.mark.parametrize("shape", [(1, 5, 5), (2, 37, 45), (1, 64, 64), (3, 100, 33), (1, 1, 9), (1, 7, 1),
+                                   (1, 2, 3), (2, 3, 4), (1, 300, 130), (1, 70, 260)])
 def test_forward_backward_small(oracle_mod, sobel_lib, gpu, border, shape):
+    """Every border rule, on shapes that span several column strips and row
+    chunks (130, 260 columns; 300 rows) and on images so small that the
+    reflection repeats (1 to 4 rows or columns)."""
     b, h, w = shape
     if border == 1 and min(h, w) < 5:
         pytest.skip("VALID needs 5x5")
@@ -88,14 +92,15 @@ def test_tiny_magnitudes(oracle_mod, sobel_lib, gpu):
     check_bwd(oracle_mod, x, g, dx.cpu().numpy(), 0)
 
 
-def test_autograd_function(oracle_mod, sobel_lib, gpu):
+@pytest.mark.parametrize("border", [0, 3])
+def test_autograd_function(oracle_mod, sobel_lib, gpu, border):
     from paper_2305_00515_amd import sobel4x5_magnitude
     x = f32_batch(2, 48, 40, 5)
     xt = torch.from_numpy(x).to(gpu).requires_grad_(True)
-    loss = sobel4x5_magnitude(xt).mean()
+    loss = sobel4x5_magnitude(xt, border).mean()
     loss.backward()
     g = np.full((2, 48, 40), 1.0 / x.size, np.float32)
-    check_bwd(oracle_mod, x, g, xt.grad.cpu().numpy(), 0)
+    check_bwd(oracle_mod, x, g, xt.grad.cpu().numpy(), border)
 
 
 def test_config4_fd_and_oracle_gradient(oracle_mod, sobel_lib, gpu):
