@@ -9,14 +9,20 @@
 //   G_k(p) = sum over the 12 taps (i, j) of the upper half
 //            k[i][j] * (I(p + (i-2, j-2)) - I(p + (2-i, 2-j)))
 //
-// The 12 pair differences are shared by the four responses, so a pixel
-// costs 12 subtractions and 48 multiply-adds (v_mad_i32_i24: |k| < 2^23,
-// |difference| <= 255), all exact in int32 for the weight bounds the host
-// checks.  The magnitude rounds min(255, round(sqrt(S))) exactly: every
-// |G_k| is clamped at 256 first, which changes S only where S >= 65536 and
-// the result saturates anyway, so S stays below 2^24 and its float square
-// root rounds correctly (no integer S is within 4.9e-4 of a half-integer
-// root).  The paper's own factoring (Eq. (sobel5_kd+-), (sobel5_4)) serves
+// The 12 pair differences are shared by the four responses.  They are
+// formed two at a time as int16 pairs (|difference| <= 255), and each
+// response is six v_dot2_i32_i16 against int16 pairs of coefficients:
+// antisymmetry puts every weight twice into sum |k| <= 32768, so |k| <=
+// 16384 fits int16, and |G| <= 255 * 16384 stays far inside int32.  The
+// pairs: taps (i, j), (i, j+1) of one row meet the partner row's bytes in
+// reverse order, so each input row is packed once, as it enters the ring,
+// into adjacent-byte pairs in both orders; the two taps left over, (0, 4)
+// and (1, 4), form the sixth pair.  The magnitude rounds min(255,
+// round(sqrt(S))) exactly: every G_k is clamped to [-256, 256] first, which
+// changes S only where S >= 65536 and the result saturates anyway, so S
+// stays below 2^24 and its float square root rounds correctly (no integer S
+// is within 4.9e-4 of a half-integer root); the clamped responses are
+// squared and summed with v_dot2 as well.  The paper's own factoring (Eq. (sobel5_kd+-), (sobel5_4)) serves
 // the default weights on the packed fast path.
 //
 // Work layout: a lane owns 4 consecutive output pixels of a row and walks a
@@ -41,20 +47,41 @@ constexpr int kPplW = 4;                 // output pixels per lane
 constexpr int kColsW = 64 * kPplW;       // output columns per wave
 
 typedef unsigned int u32;
+typedef short v2s __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// Sign-extend from 24 bits: a no-op for the coefficients (the host checks
-// |k| < 2^23) that lets the products use the full-rate 24-bit multiplier.
-__device__ __forceinline__ int s24(int v) { return (v << 8) >> 8; }
+__device__ __forceinline__ v2s V2(u32 v) { return __builtin_bit_cast(v2s, v); }
+__device__ __forceinline__ u32 U2(v2s v) { return __builtin_bit_cast(u32, v); }
+// low 16 bits of lo, then low 16 bits of hi
+__device__ __forceinline__ u32 pair16(u32 lo, u32 hi) { return __builtin_amdgcn_perm(hi, lo, 0x05040100u); }
+__device__ __forceinline__ int dot2(v2s a, v2s b, int c) { return __builtin_amdgcn_sdot2(a, b, c, false); }
+// a.lo*b.lo + a.hi*b.hi with no accumulator: the three-operand form with an
+// inline 0 (the compiler otherwise clears a register for the two-operand
+// accumulate-in-place form)
+__device__ __forceinline__ int dot2_0(v2s a, v2s b)
+{
+    int r;
+    asm("v_dot2_i32_i16 %0, %1, %2, 0" : "=v"(r) : "v"(U2(a)), "v"(U2(b)));
+    return r;
+}
+__device__ __forceinline__ int dot2_0s(v2s a, u32 b_uniform)
+{
+    int r;
+    asm("v_dot2_i32_i16 %0, %1, %2, 0" : "=v"(r) : "v"(U2(a)), "s"(b_uniform));
+    return r;
+}
 
 template <int P>
 using PhW = std::integral_constant<int, P>;
 
-// Upper-half taps (i, j) in the order of the coefficient table: row 0, row 1,
-// then (2, 0), (2, 1); the partner tap is (4 - i, 4 - j).
-__device__ __forceinline__ constexpr int tap_i(int t) { return t < 5 ? 0 : (t < 10 ? 1 : 2); }
-__device__ __forceinline__ constexpr int tap_j(int t) { return t < 10 ? t % 5 : t - 10; }
+// Upper-half taps u in the order of the coefficient table: (0, 0..4) are
+// u = 0..4, (1, 0..4) are 5..9, (2, 0), (2, 1) are 10, 11; the partner of
+// tap (i, j) is (4 - i, 4 - j).  The six pairs of taps whose differences
+// share one v_dot2:
+//   (0,0)(0,1)  (0,2)(0,3)  (1,0)(1,1)  (1,2)(1,3)  (2,0)(2,1)  (0,4)(1,4)
+__device__ constexpr int kPairLo[6] = {0, 2, 5, 7, 10, 4};
+__device__ constexpr int kPairHi[6] = {1, 3, 6, 8, 11, 9};
 
 // BM: how pixels outside the image read (0 nearest, 1 zero, 2 reflect-101).
 template <int OFF, int DT, int BM>
@@ -92,8 +119,20 @@ __global__ __launch_bounds__(64 * kWavesW) void k_u8_weighted(WJob J, int nstrip
         return (unsigned)r <= (unsigned)(J.H - 1) ? colin : 0u;
     };
 
-    // bytes, so that every pair difference is known to fit 24 bits
-    uint8_t ring[5][kPplW + 4], pf[5][kPplW + 4];
+    // coefficient pairs (k[lo], k[hi]) as int16 halves, wave-uniform
+    u32 cp[4][6];
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl)
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            cp[pl][q] = (u32)(uint16_t)J.coef[pl][kPairLo[q]] | ((u32)(uint16_t)J.coef[pl][kPairHi[q]] << 16);
+
+    // Ring of packed input rows, R the row's 8 window bytes (low half
+    // first): F[c] = (R[c], R[c+1]) for c = 0..5, and B[c] = (R[c+2], R[c+1])
+    // for c = 0..5, the reversed pair that starts at c + 1.  R[c] is the low
+    // half of F[c] (c <= 5) or of B[c-2] (c = 6, 7).
+    u32 F[5][6], B[5][6];
+    uint8_t pf[5][kPplW + 4];
     constexpr int PD = 2;   // rows loaded ahead
 #pragma unroll
     for (int t = 0; t < PD; ++t) {
@@ -104,31 +143,45 @@ __global__ __launch_bounds__(64 * kWavesW) void k_u8_weighted(WJob J, int nstrip
     auto step = [&](int t, auto phase) {
         constexpr int p = decltype(phase)::value;
         ldrow(t + PD, pf[(p + PD) % 5]);
-        if constexpr (BM == 1) {
-            const u32 in = inside(t);
+        {
+            u32 b[kPplW + 4];
+            if constexpr (BM == 1) {
+                const u32 in = inside(t);
 #pragma unroll
-            for (int j = 0; j < kPplW + 4; ++j) ring[p][j] = ((in >> j) & 1u) ? pf[p][j] : (uint8_t)0;
-        } else {
+                for (int j = 0; j < kPplW + 4; ++j) b[j] = ((in >> j) & 1u) ? (u32)pf[p][j] : 0u;
+            } else {
 #pragma unroll
-            for (int j = 0; j < kPplW + 4; ++j) ring[p][j] = pf[p][j];
+                for (int j = 0; j < kPplW + 4; ++j) b[j] = pf[p][j];
+            }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                F[p][c] = b[c] | (b[c + 1] << 16);
+                B[p][c] = b[c + 2] | (b[c + 1] << 16);
+            }
         }
         if (t < 4) return;
         // window row i (0..4) = input row t - 4 + i, in slot (p + 1 + i) % 5
+        constexpr int w0 = (p + 1) % 5, w1 = (p + 2) % 5, w2 = (p + 3) % 5, w3 = (p + 4) % 5, w4 = p;
+        auto lo16 = [&](const u32 (&f)[6], const u32 (&r)[6], int c) -> u32 { return c <= 5 ? f[c] : r[c - 2]; };
         const int yo = y0 + t - 4;
         int G[kPplW][4];
 #pragma unroll
         for (int q = 0; q < kPplW; ++q) {
-            int d[12];
-#pragma unroll
-            for (int u = 0; u < 12; ++u) {
-                const int i = tap_i(u), jj = tap_j(u);
-                d[u] = (int)ring[(p + 1 + i) % 5][q + jj] - (int)ring[(p + 1 + 4 - i) % 5][q + 4 - jj];
-            }
+            // pair (j, j+1) of row i: F[q + j] of row i minus the reversed
+            // pair of row 4 - i that starts at q + 3 - j, B[q + 2 - j]
+            v2s d[6];
+            d[0] = V2(F[w0][q]) - V2(B[w4][q + 2]);
+            d[1] = V2(F[w0][q + 2]) - V2(B[w4][q]);
+            d[2] = V2(F[w1][q]) - V2(B[w3][q + 2]);
+            d[3] = V2(F[w1][q + 2]) - V2(B[w3][q]);
+            d[4] = V2(F[w2][q]) - V2(B[w2][q + 2]);
+            d[5] = V2(pair16(lo16(F[w0], B[w0], q + 4), lo16(F[w1], B[w1], q + 4))) -
+                   V2(pair16(F[w4][q], F[w3][q]));
 #pragma unroll
             for (int pl = 0; pl < 4; ++pl) {
-                int acc = 0;
+                int acc = dot2_0s(d[0], cp[pl][0]);
 #pragma unroll
-                for (int u = 0; u < 12; ++u) acc += s24(J.coef[pl][u]) * d[u];
+                for (int u = 1; u < 6; ++u) acc = dot2(d[u], V2(cp[pl][u]), acc);
                 G[q][pl] = acc;
             }
         }
@@ -137,14 +190,13 @@ __global__ __launch_bounds__(64 * kWavesW) void k_u8_weighted(WJob J, int nstrip
             const int nvalid = J.Wo - xo;
 #pragma unroll
             for (int q = 0; q < kPplW; ++q) {
-                int S = 0;
+                int g[4];
 #pragma unroll
-                for (int pl = 0; pl < 4; ++pl) {
-                    const int g = min(abs(G[q][pl]), 256);
-                    S += g * g;
-                }
-                const u32 m = S >= 65281 ? 255u
-                                         : __builtin_amdgcn_cvt_pk_u8_f32(__builtin_amdgcn_sqrtf((float)S), 0, 0u);
+                for (int pl = 0; pl < 4; ++pl) g[pl] = min(max(G[q][pl], -256), 256);
+                const v2s g01 = V2(pair16((u32)g[0], (u32)g[1])), g23 = V2(pair16((u32)g[2], (u32)g[3]));
+                const int S = dot2(g01, g01, dot2_0(g23, g23));
+                // v_cvt_pk_u8_f32 rounds to nearest and saturates at 255
+                const u32 m = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_amdgcn_sqrtf((float)S), 0, 0u);
                 out |= m << (8 * q);
             }
             GMEM uint8_t *mp = (GMEM uint8_t *)J.mag + (int64_t)yo * J.mag_pitch + (xo < 0 ? 0 : xo);

@@ -57,6 +57,32 @@ def test_random_antisymmetric_kernels(oracle_mod, sobel_lib, gpu):
             assert np.array_equal(mag, om) and np.array_equal(d, od), trial
 
 
+def test_weights_at_the_int16_limit(oracle_mod, sobel_lib, gpu):
+    """Antisymmetry puts each weight twice into sum |k| <= 32768, so |k| <=
+    16384: the largest kernels the host accepts, with weights of +-16384 and
+    a mix of signs that fills the whole budget, under all four borders."""
+    rng = np.random.default_rng(5)
+    w = np.zeros((4, 5, 5), np.int64)
+    w[0, 0, 0], w[0, 4, 4] = 16384, -16384                      # one pair at the limit
+    w[1, 1, 3], w[1, 3, 1] = -16384, 16384
+    for k in (2, 3):                                            # 12 random pairs, sum |k| = 32768
+        v = rng.integers(1, 2000, 12).astype(np.float64)
+        v = np.floor(v / v.sum() * 16384).astype(np.int64)
+        v[0] += 16384 - v.sum()
+        v *= rng.choice([-1, 1], 12)
+        taps = [(i, j) for i in range(3) for j in range(5) if (i, j) < (2, 2)]
+        for (i, j), x in zip(taps, v):
+            w[k, i, j], w[k, 4 - i, 4 - j] = x, -x
+    assert np.abs(w).sum(axis=(1, 2)).max() == 32768 and np.abs(w).max() == 16384
+    img = synth.rect_image(37, 130, 77)
+    low = (img % 3).astype(np.uint8)
+    for border in (0, 1, 2, 3):
+        for im in (img, low):
+            mag, d = run(sobel_lib, im, gpu, w.astype(np.int32), border, sobel_lib.DIR_S32)
+            om, od = oracle_mod.sobel_u8(im, border, weights=w.astype(np.int32))
+            assert np.array_equal(mag, om) and np.array_equal(d, od), border
+
+
 def test_default_weights_match_fast_path(sobel_lib, gpu):
     """The weighted path with Eq. (sobel5_1) equals the packed default path."""
     img = synth.field_image(300, 1000, 9)
