@@ -190,12 +190,37 @@ def test_pipeline(oracle_mod, sobel_lib, gpu, border):
         assert np.array_equal(o, oracle_mod.sobel_u8(m, border, want_dir=False)[0]), m.shape
 
 
-def test_fp32_rejects_the_new_borders(sobel_lib, gpu):
-    x = torch.zeros((1, 8, 8), device=gpu)
-    for b in NEW:
-        with pytest.raises(sobel_lib.SobelError) as e:
-            sobel_lib.sobel4x5_f32_fwd(x, b)
-        assert e.value.code == sobel_lib.EUNSUPPORTED
+@pytest.mark.parametrize("border", NEW)
+def test_fp32_pitched_buffers_through_the_c_abi(oracle_mod, sobel_lib, gpu, border):
+    """The fp32 pair under the new borders on row-pitched, batch-strided
+    buffers (rows padded to 80 floats, images 7 rows apart), called through
+    the C ABI with raw pointers; pixels of the padding stay untouched."""
+    api = sobel_lib
+    b, h, w, wp, hp = 2, 33, 70, 80, 40
+    x = np.stack([synth.rect_image(h, w, 60 + i) for i in range(b)]).astype(np.float32) / np.float32(255)
+    xs = torch.full((b, hp, wp), 7.0, device=gpu)
+    xs[:, :h, :w] = torch.from_numpy(x).to(gpu)
+    m = torch.full((b, hp, wp), -1.0, device=gpu)
+    g = np.random.default_rng(3).standard_normal((b, h, w)).astype(np.float32)
+    gs = torch.full((b, hp, wp), 9.0, device=gpu)
+    gs[:, :h, :w] = torch.from_numpy(g).to(gpu)
+    dx = torch.full((b, hp, wp), -2.0, device=gpu)
+    pitch, bstride = wp * 4, hp * wp * 4
+    rc = api.lib.sobel4x5_f32_fwd(xs.data_ptr(), b, w, h, pitch, bstride, border, m.data_ptr(), pitch, bstride, None)
+    assert rc == 0
+    rc = api.lib.sobel4x5_f32_bwd(xs.data_ptr(), pitch, bstride, gs.data_ptr(), pitch, bstride, b, w, h, border,
+                                  dx.data_ptr(), pitch, bstride, None)
+    assert rc == 0
+    torch.cuda.synchronize()
+    M, D = m.cpu().numpy(), dx.cpu().numpy()
+    Mr, _ = oracle_mod.sobel_f64_fwd(x.astype(np.float64), border)
+    s = oracle_mod.sobel_f64_fwd_scale(x.astype(np.float64), border)
+    assert np.all(np.abs(M[:, :h, :w] - Mr) <= 1e-5 * np.maximum(Mr, s) + 1e-30)
+    ref = oracle_mod.sobel_f64_bwd(x.astype(np.float64), g.astype(np.float64), border)
+    A = oracle_mod.sobel_f64_bwd_scale(x.astype(np.float64), g.astype(np.float64), border)
+    assert np.all(np.abs(D[:, :h, :w] - ref) <= 1e-5 * A + 1e-30)
+    assert np.all(M[:, h:, :] == -1.0) and np.all(M[:, :, w:] == -1.0)
+    assert np.all(D[:, h:, :] == -2.0) and np.all(D[:, :, w:] == -2.0)
 
 
 def test_batched_mixed_outputs_through_the_c_abi(oracle_mod, sobel_lib, gpu):
