@@ -171,14 +171,30 @@ int env_int(const char *name, int dflt)
 // kernel keeps more values live).  SOBEL4X5_U8_PPL (8 or 16),
 // SOBEL4X5_U8_WAVES (waves to launch) and SOBEL4X5_U8_MIN_ROWS (fewest rows
 // per wave) override the choice for tuning runs.
+// Compute units of the current device (cached per device; 256 if unknown).
+int device_cus()
+{
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int n = cache[dev].load(std::memory_order_relaxed);
+    if (n > 0) return n;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cache[dev].store(n, std::memory_order_relaxed);
+    return n;
+}
+
 U8Shape default_shape(int32_t Wo, int32_t Ho, int32_t dir_type)
 {
-    (void)Ho;
     U8Shape s;
-    // 16 pixels per lane from 1536 columns up; narrower images have too few
-    // waves to fill the chip, and halving each wave's serial work wins
-    // (1024^2 magnitude: 4.0 against 5.0 us per launch)
-    s.ppl = (Wo >= 1536 && dir_type == SOBEL4X5_DIR_NONE) ? 16 : 8;
+    // 16 pixels per lane (1024-column strips) only where that shape alone
+    // fills one round of resident waves (2 per SIMD, 8 per CU) with its
+    // 2-row minimum ranges.  Smaller images have too few waves, and 8 pixels
+    // per lane doubles them and halves each one's serial work (1024^2:
+    // 4.55 against 5.42 us per launch, 1920x1080: 6.5 against 7.3 us).
+    const int64_t strips16 = (Wo + 1023) / 1024;
+    const bool fills = strips16 * (Ho / 2) >= 8 * (int64_t)device_cus();
+    s.ppl = (fills && dir_type == SOBEL4X5_DIR_NONE) ? 16 : 8;
     const int ppl = env_int("SOBEL4X5_U8_PPL", 0);
     if (ppl == 8 || ppl == 16) s.ppl = ppl;
     s.th = 32;
