@@ -757,10 +757,10 @@ int sobel4x5_u8_op(const uint8_t *src, int32_t width, int32_t height, int64_t sr
     u8_tile(j, s);
     // The two-directional operators are lighter on arithmetic, so the 4-row
     // prologue each wave re-reads weighs more: on large images they take
-    // 32-row ranges as long as 2048 waves remain (8192^2 3x3: 2128 -> 2232
-    // Gpx/s).
+    // 32-row ranges as long as one round of resident waves (8 per CU)
+    // remains (8192^2 3x3: 2128 -> 2232 Gpx/s).
     if (out->dir_type == SOBEL4X5_DIR_NONE && env_int("SOBEL4X5_U8_MIN_ROWS", 0) == 0 &&
-        (int64_t)((j.ntx + 3) / 4) * (Ho / 32) >= 2048)
+        (int64_t)((j.ntx + 3) / 4) * (Ho / 32) >= 8 * (int64_t)device_cus())
         s.min_rows = 32;
     hipError_t e = launch_u8_2dir(j, op, border, s, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_u8_op launch");
