@@ -171,6 +171,10 @@ int env_int(const char *name, int dflt)
 // kernel keeps more values live).  SOBEL4X5_U8_PPL (8 or 16),
 // SOBEL4X5_U8_WAVES (waves to launch) and SOBEL4X5_U8_MIN_ROWS (fewest rows
 // per wave) override the choice for tuning runs.
+// U8Shape::waves of a batched plan that launches one wave per tile (static
+// form, no work queue) instead of a persistent grid.
+constexpr int kStaticGrid = 1 << 30;
+
 // Compute units of the current device (cached per device; 256 if unknown).
 int device_cus()
 {
@@ -371,19 +375,24 @@ int plan_setup(sobel4x5_plan_s *p, const U8Shape &shape)
         plan_free_device(p);
         return hip_fail(e, "uploading plan tables");
     }
+    const int need = (p->total + 3) / 4;   // never more workgroups than work (4 waves each)
+    if (shape.waves == kStaticGrid) {       // one wave per tile, no queue
+        p->grid = std::max(1, need);
+        return ok();
+    }
     p->grid = u8_persistent_grid(shape, p->border, p->aligned, p->dir);
     if (p->grid <= 0) {
         plan_free_device(p);
         return fail(SOBEL4X5_EHIP, "could not query occupancy");
     }
-    const int need = (p->total + 3) / 4;   // never more workgroups than work
     p->grid = std::max(1, std::min(p->grid, need));
     return ok();
 }
 
 int plan_direct_launch(sobel4x5_plan_s *p, hipStream_t st)
 {
-    hipError_t e = launch_u8_batched(p->d_jobs, p->d_tiles, p->total, p->d_queue, p->border, p->aligned, p->dir,
+    uint32_t *queue = p->shape.waves == kStaticGrid ? nullptr : p->d_queue;
+    hipError_t e = launch_u8_batched(p->d_jobs, p->d_tiles, p->total, queue, p->border, p->aligned, p->dir,
                                      p->shape, p->grid, st);
     return e == hipSuccess ? ok() : hip_fail(e, "batched launch");
 }
@@ -528,12 +537,17 @@ bool tune_lookup(const std::string &key, U8Shape &s)
 {
     FILE *f = std::fopen(tune_cache_path().c_str(), "r");
     if (!f) return false;
-    char k[512];
-    int ppl, th, wpg;
+    // one entry a line: key ppl th wpg [static]; a line without the last
+    // field is a persistent grid
+    char line[1024], k[512];
     bool found = false;
-    while (std::fscanf(f, "%511s %d %d %d", k, &ppl, &th, &wpg) == 4) {
-        if (key == k && (ppl == 8 || ppl == 16) && th >= 4 && th <= 256 && wpg == 4) {
+    while (std::fgets(line, sizeof line, f)) {
+        int ppl = 0, th = 0, wpg = 0, st = 0;
+        const int n = std::sscanf(line, "%511s %d %d %d %d", k, &ppl, &th, &wpg, &st);
+        if (n >= 4 && key == k && (ppl == 8 || ppl == 16) && th >= 4 && th <= 256 && wpg == 4 &&
+            (st == 0 || st == 1)) {
             s = U8Shape{ppl, th, wpg};
+            if (n == 5 && st == 1) s.waves = kStaticGrid;
             found = true;   // last entry wins
         }
     }
@@ -548,23 +562,33 @@ void tune_store(const std::string &key, const U8Shape &s)
     if (slash != std::string::npos && slash > 0) mkdir(path.substr(0, slash).c_str(), 0755);   // best effort
     FILE *f = std::fopen(path.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %d\n", key.c_str(), s.ppl, s.th, s.wpg);
+    std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), s.ppl, s.th, s.wpg, s.waves == kStaticGrid ? 1 : 0);
     std::fclose(f);
 }
 
-// Shape of a batched plan without autotuning: 16 pixels per lane and 32-row
-// tiles for magnitudes; with directional planes 8 pixels per lane (the
-// plane stores keep more values live) and 8-row tiles (measured on 256 mixed
-// images: 299 Gpx/s against 270 with 32-row tiles).  SOBEL4X5_BATCH_PPL (8 or
-// 16) and SOBEL4X5_BATCH_TH (4..256) override it.
+// Shape of a batched plan without autotuning.
+// - Magnitudes only: 16 pixels per lane and 32-row tiles on a persistent
+//   grid (a static grid is no faster: 1198 against 1200 Gpx/s on 256 mixed
+//   images).
+// - With directional planes, which are bound by their stores: 8 pixels per
+//   lane (the plane stores keep more values live), 4-row tiles and the
+//   static grid, one wave per tile, so that many short-lived waves keep the
+//   stores in flight: 352 Gpx/s against 299 for the persistent grid with
+//   8-row tiles.
+// SOBEL4X5_BATCH_PPL (8 or 16), SOBEL4X5_BATCH_TH (4..256) and
+// SOBEL4X5_BATCH_STATIC (0 or 1) override it.
 U8Shape batch_default_shape(const std::vector<sobel4x5_image> &imgs, bool dir)
 {
     (void)imgs;
-    U8Shape s{dir ? 8 : 16, dir ? 8 : 32, 4};
+    U8Shape s{dir ? 8 : 16, dir ? 4 : 32, 4};
+    if (dir) s.waves = kStaticGrid;
     const int ppl = env_int("SOBEL4X5_BATCH_PPL", 0);
     if (ppl == 8 || ppl == 16) s.ppl = ppl;
     const int th = env_int("SOBEL4X5_BATCH_TH", 0);
     if (th >= 4 && th <= 256) s.th = th;
+    const int st = env_int("SOBEL4X5_BATCH_STATIC", -1);
+    if (st == 0) s.waves = 0;
+    if (st == 1) s.waves = kStaticGrid;
     return s;
 }
 
@@ -589,7 +613,7 @@ int plan_autotune(sobel4x5_plan_s *p)
     for (int ppl : ppls)
         for (int th : ths) {
             const U8Shape c{ppl, th, 4};
-            if (c.ppl == ref.ppl && c.th == ref.th) continue;
+            if (c.ppl == ref.ppl && c.th == ref.th && c.waves == ref.waves) continue;
             if (plan_setup(p, c) != SOBEL4X5_OK) continue;
             // clear outputs so that a candidate that skips pixels cannot pass
             for (int32_t i = 0; i < p->count; ++i)

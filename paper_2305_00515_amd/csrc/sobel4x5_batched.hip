@@ -43,7 +43,8 @@ __device__ __forceinline__ Sweep batch_geometry(const U8Job &J, const int4 &ti, 
 
 // Persistent work-queue kernel: every wave takes the next wave-tile of the
 // whole batch from queue[0] until none are left, then counts itself out in
-// queue[1]; the last wave out resets both words for the next launch.  A
+// queue[1]; the last wave out resets both words for the next launch.  With
+// queue == nullptr the grid holds one wave per tile instead (static form).  A
 // ticket indexes the host-built tile table, so finding a tile is one load.
 // DIR: images whose job asks for them also get their directional planes.
 // The sweeps here cover short row ranges (tiles of a few tens of rows) and
@@ -57,16 +58,13 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
 {
     constexpr int TW = 16 * PPL;
     const int lane = threadIdx.x & 63;
-    for (;;) {
-        u32 tv = 0;
-        if (lane == 0) tv = atomicAdd(&queue[0], 1u);
-        const int t = __builtin_amdgcn_readfirstlane((int)tv);
-        if (t >= total) break;
+    // one tile of the table: returns false when it has no rows
+    auto run_tile = [&](int t) __attribute__((always_inline)) {
         const int4 ti = tiles[t];
         const U8Job J = jobs[ti.x];
         Sweep g = batch_geometry(J, ti, PPL, TH);
         g.fix_left = g.fix_left && OFF == 0;
-        if (g.niter <= 0) continue;
+        if (g.niter <= 0) return;
         // fast: every group has its full rows, every lane's block and output
         // inside the image
         bool fast;
@@ -83,6 +81,19 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
             sweep<PPL, OFF, ALIGNED, DIR, true, true, kOp4x5, BM, false>(J, g);
         else
             sweep<PPL, OFF, ALIGNED, DIR, false, false, kOp4x5, BM, false>(J, g);
+    };
+    if (queue == nullptr) {
+        // static form: wave w of the grid takes tile w, no queue
+        const int t = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        if (t < total) run_tile(t);
+        return;
+    }
+    for (;;) {
+        u32 tv = 0;
+        if (lane == 0) tv = atomicAdd(&queue[0], 1u);
+        const int t = __builtin_amdgcn_readfirstlane((int)tv);
+        if (t >= total) break;
+        run_tile(t);
     }
     if (lane == 0) {
         __threadfence();
