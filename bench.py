@@ -411,7 +411,7 @@ def bench_copy(torch, api, dev, steps):
 # and WRITE_SIZE (KiB per dispatch), scaled by what the same counters read for
 # the plain copy kernel (sobel4x5_debug_copy) of known size.  Valid only for
 # the kernel source they were taken on (its SHA-256 prefix); None otherwise.
-U8_TRAFFIC = {"src_sha256": "f32f9ced96bc6bdf", "bytes": 145189884}   # profiles/k_u8_single_8192x8192_mag_u8.md
+U8_TRAFFIC = {"src_sha256": "f32f9ced96bc6bdf", "bytes": 145204014}   # profiles/k_u8_single_8192x8192_mag_u8.md
 
 
 # Sources k_u8_single is compiled from (the hash covers them in this order);
