@@ -149,6 +149,36 @@ def test_batched_directional_planes(oracle_mod, sobel_lib, gpu, border, dir_type
         assert np.array_equal(d, od), m.shape
 
 
+@pytest.mark.parametrize("static", ["0", "1"])
+@pytest.mark.parametrize("planes", [False, True])
+def test_batched_grid_forms(oracle_mod, sobel_lib, gpu, monkeypatch, static, planes):
+    """Both grid forms of the batched kernel, for magnitudes and for planes:
+    the persistent grid with its work queue (which the last wave resets for
+    the next launch) and the static grid of one wave per tile, each plan
+    replayed three times with the outputs poisoned in between."""
+    monkeypatch.setenv("SOBEL4X5_BATCH_STATIC", static)
+    imgs = batch_images()
+    srcs = [dev_image(m, gpu, synth.round_up(m.shape[1], 16)) for m in imgs]
+    mags = [torch.empty(m.shape, dtype=torch.uint8, device=gpu) for m in imgs]
+    dirs = [[torch.empty(m.shape, dtype=torch.int16, device=gpu) for _ in range(4)] for m in imgs] if planes else None
+    plan = (sobel_lib.Plan(srcs, mags, REFLECT101, dir_type=1, dirs=dirs) if planes
+            else sobel_lib.Plan(srcs, mags, REFLECT101))
+    for _ in range(3):
+        for t in mags:
+            t.fill_(7)
+        for ps in dirs or []:
+            for t in ps:
+                t.fill_(7)
+        plan.launch()
+        torch.cuda.synchronize()
+        for i, m in enumerate(imgs):
+            om, od = oracle_mod.sobel_u8(m, REFLECT101)
+            assert np.array_equal(mags[i].cpu().numpy(), om), m.shape
+            if planes:
+                assert np.array_equal(np.stack([x.cpu().numpy() for x in dirs[i]]).astype(np.int32), od), m.shape
+    plan.close()
+
+
 def test_batched_planes_only_unaligned_and_autotuned_plan(oracle_mod, sobel_lib, gpu, tmp_path, monkeypatch):
     """Planes without magnitudes, unaligned sources (byte path), and an
     autotuned plan whose candidate shapes are checked on every plane."""
