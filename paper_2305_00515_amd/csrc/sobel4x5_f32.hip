@@ -17,9 +17,10 @@
 // pixel is centred.  Every factor pair is applied down the columns first;
 // the five column results then meet in one correlation across the columns
 // whose taps are the matching combinations of the five row filters, so the
-// adjoint needs only four lane shifts per row.  The replicate border then
-// folds P at the two virtual rows and columns beyond each edge onto that
-// edge.
+// adjoint needs only four lane shifts per row.  P at the two virtual rows
+// and columns beyond each edge then goes to the pixel the border rule read
+// there: the edge pixel (replicate), the mirror pixel (reflect-101), or
+// nowhere (zero: those taps read a constant).
 //
 // Layout of the work: a wave owns a strip of columns and a range of rows of
 // one image.  Each lane holds two adjacent columns and walks down the rows,
