@@ -22,12 +22,13 @@
 // changes S only where S >= 65536 and the result saturates anyway, so S
 // stays below 2^24 and its float square root rounds correctly (no integer S
 // is within 4.9e-4 of a half-integer root); the clamped responses are
-// squared and summed with v_dot2 as well.  The paper's own factoring (Eq. (sobel5_kd+-), (sobel5_4)) serves
-// the default weights on the packed fast path.
+// squared and summed with v_dot2 as well.  The paper's own factoring
+// (Eq. (sobel5_kd+-), (sobel5_4)) serves the default weights on the packed
+// fast path.
 //
 // Work layout: a lane owns 4 consecutive output pixels of a row and walks a
-// range of rows with a 5-row register ring of the 8 input bytes it needs;
-// a wave covers 256 columns.
+// range of rows with a 5-row register ring of the int16 pairs packed from
+// the 8 input bytes it needs; a wave covers 256 columns.
 
 #include "internal.hpp"
 #include "load_columns.hpp"
