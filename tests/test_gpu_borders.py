@@ -207,6 +207,16 @@ def test_batched_planes_only_unaligned_and_autotuned_plan(oracle_mod, sobel_lib,
             om, od = oracle_mod.sobel_u8(m, ZERO)
             assert np.array_equal(g.cpu().numpy(), om)
             assert np.array_equal(np.stack([x.cpu().numpy() for x in ps]).astype(np.int32), od)
+    # a second plan is served from the cache file, grid form included
+    plan2 = sobel_lib.Plan(srcs, mags, ZERO, autotune=True, dir_type=1, dirs=dirs)
+    assert plan2.info() == plan.info()
+    for t in mags:
+        t.fill_(7)
+    plan2.launch()
+    torch.cuda.synchronize()
+    for m, g in zip(imgs, mags):
+        assert np.array_equal(g.cpu().numpy(), oracle_mod.sobel_u8(m, ZERO)[0])
+    plan2.close()
     plan.close()
 
 
