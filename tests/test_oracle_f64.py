@@ -5,7 +5,9 @@ replicate, zero, or a reflect-101 gather whose indices come from numpy's
 'reflect' pad, which also covers images smaller than the pad) and to the
 oracle's own integer path on integer images.  The adjoint is pinned to
 torch's reverse-mode autograd through that same library forward (fp64, safe
-square root) and to central finite differences.
+square root), to central finite differences, and by the adjoint dot-product
+identity against the forward's own linear responses.  The two tolerance
+scales are pinned by exact closed forms (constant and impulse images).
 """
 import numpy as np
 import pytest
@@ -130,3 +132,137 @@ def test_error_scales_bound_the_results(oracle_mod, border):
     assert np.all(A >= 0)
     # a constant image has no terms at all
     assert not oracle_mod.sobel_f64_bwd_scale(np.full((1, 8, 8), 0.7), np.ones((1, 8, 8))).any()
+
+
+# ----------------------------------------------------------------------------
+# Exact pins of the two tolerance scales.  The scales set how far an fp32
+# result may sit from the fp64 oracle, so a mistake that inflates them (a sum
+# over the four filters instead of the largest one, a tap counted twice, a
+# missing absolute value, the filter applied transposed) would loosen every
+# fp32 parity check.  Each pin is a closed form worked out from the printed
+# matrices of Eq. (sobel5_1) (tests/golden/eq_sobel5_1.txt) for an input on
+# which the definition collapses to one term.
+# ----------------------------------------------------------------------------
+
+import os  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def golden_weights():
+    mats, cur, name = {}, [], None
+    with open(os.path.join(GOLDEN, "eq_sobel5_1.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            if line.startswith("["):
+                if name:
+                    mats[name] = np.array(cur, dtype=np.float64)
+                name, cur = line[1:-1], []
+            else:
+                cur.append([float(v) for v in line.split()])
+    mats[name] = np.array(cur, dtype=np.float64)
+    return np.stack([mats[p] for p in ("Gx", "Gd", "Gy", "Gdt")])
+
+
+@pytest.mark.parametrize("border", [0, 1, 3])
+def test_fwd_scale_constant_image_is_96c(oracle_mod, border):
+    """Every filter has sum |w| = 96, and a constant image c feeds c to every
+    tap under REPLICATE, VALID and REFLECT101: the scale is exactly 96c."""
+    K = golden_weights()
+    assert np.all(np.abs(K).sum(axis=(1, 2)) == 96)
+    x = np.full((2, 9, 12), 3.0)
+    s = oracle_mod.sobel_f64_fwd_scale(x, border)
+    assert np.all(s == 288.0)
+
+
+def test_fwd_scale_zero_border_counts_only_taps_inside(oracle_mod):
+    """Under ZERO a tap outside reads 0: at the corner pixel of a constant
+    image only the taps (i, j) with i, j >= 2 read c, so the scale is c times
+    the largest sum of |w| over that quarter of a filter."""
+    K = golden_weights()
+    x = np.full((1, 10, 10), 2.0)
+    s = oracle_mod.sobel_f64_fwd_scale(x, 2)
+    corner = 2.0 * np.abs(K[:, 2:, 2:]).sum(axis=(1, 2)).max()
+    assert s[0, 0, 0] == corner
+    assert np.all(s[0, 2:-2, 2:-2] == 192.0)
+
+
+def test_fwd_scale_impulse_is_largest_single_tap(oracle_mod):
+    """Impulse V at c: output q = c + (dy, dx) sees one nonzero tap, (2-dy,
+    2-dx), so the scale is V * max_k |K_k[2-dy][2-dx]| and 0 farther away."""
+    K = golden_weights()
+    V, c = 5.0, 7
+    x = np.zeros((1, 15, 15))
+    x[0, c, c] = V
+    s = oracle_mod.sobel_f64_fwd_scale(x)[0]
+    want = np.zeros((15, 15))
+    for dy in range(-2, 3):
+        for dx in range(-2, 3):
+            want[c + dy, c + dx] = V * np.abs(K[:, 2 - dy, 2 - dx]).max()
+    assert np.array_equal(s, want)
+    # planted mistakes this pin catches: a sum over the filters, a doubled tap
+    summed = np.zeros_like(want)
+    for dy in range(-2, 3):
+        for dx in range(-2, 3):
+            summed[c + dy, c + dx] = V * np.abs(K[:, 2 - dy, 2 - dx]).sum()
+    assert not np.array_equal(summed, s)
+    assert not np.array_equal(2 * s, s)
+
+
+# (dy, dx, catches_signed, catches_transposed): whether the tap of that
+# offset makes the two planted mistakes visible (they need mixed signs among
+# the G_k, and unequal weights on |K_x| and |K_y| = |K_x|^T respectively)
+@pytest.mark.parametrize("dy,dx,sgn,trn", [(1, -2, True, True), (-1, 1, True, False), (2, 2, False, False)])
+def test_bwd_scale_single_output_closed_form(oracle_mod, dy, dx, sgn, trn):
+    """Impulse image (V at c) and dL/dM nonzero (g) at one output q0 = c +
+    (dy, dx) only.  Then G_k(q0) = V K_k[2-dy][2-dx], u_k = g G_k / M, and
+    the scale at q0 + (i-2, j-2) is sum_k |K_k[i][j]| |u_k|; 0 elsewhere."""
+    K = golden_weights()
+    V, c, g0 = 3.0, 8, -0.75
+    H = W = 17
+    x = np.zeros((1, H, W))
+    x[0, c, c] = V
+    g = np.zeros((1, H, W))
+    q = (c + dy, c + dx)
+    g[0, q[0], q[1]] = g0
+    A = oracle_mod.sobel_f64_bwd_scale(x, g)[0]
+    G = V * K[:, 2 - dy, 2 - dx]
+    M = np.sqrt((G * G).sum())
+    u = g0 * G / M
+    want = np.zeros((H, W))
+    for i in range(5):
+        for j in range(5):
+            want[q[0] + i - 2, q[1] + j - 2] = (np.abs(K[:, i, j]) * np.abs(u)).sum()
+    np.testing.assert_allclose(A, want, rtol=1e-14, atol=0)
+    # planted mistakes this pin catches: signed u, transposed filters
+    signed = np.zeros((H, W))
+    transposed = np.zeros((H, W))
+    for i in range(5):
+        for j in range(5):
+            signed[q[0] + i - 2, q[1] + j - 2] = (np.abs(K[:, i, j]) * u).sum()
+            transposed[q[0] + i - 2, q[1] + j - 2] = (np.abs(K[:, j, i]) * np.abs(u)).sum()
+    assert (np.abs(signed - A).max() > 1e-3 * A.max()) == sgn
+    assert (np.abs(transposed - A).max() > 1e-3 * A.max()) == trn
+
+
+@pytest.mark.parametrize("border", [0, 1, 2, 3])
+def test_adjoint_dot_product(oracle_mod, border):
+    """<J d, v> = <d, J^T v> for the magnitude map linearised at x.  The
+    responses are linear in the image under every border rule, so J d is
+    exactly sum_k G_k[x] G_k[d] / M[x], formed from the oracle's own forward
+    planes (0 where M = 0, the subgradient the adjoint takes: the corners
+    under REFLECT101, whose mirrored window is symmetric about its centre);
+    J^T v is the oracle's adjoint."""
+    rng = np.random.default_rng(17 + border)
+    x = rng.random((2, 13, 16))
+    d = rng.standard_normal(x.shape)
+    M, Gx = oracle_mod.sobel_f64_fwd(x, border, want_dir=True)
+    _, Gd = oracle_mod.sobel_f64_fwd(d, border, want_dir=True)
+    assert (M > 0).mean() > 0.95
+    Jd = np.where(M > 0, (Gx * Gd).sum(axis=1) / np.where(M > 0, M, 1.0), 0.0)
+    v = rng.standard_normal(M.shape)
+    JTv = oracle_mod.sobel_f64_bwd(x, v, border)
+    lhs, rhs = float((Jd * v).sum()), float((d * JTv).sum())
+    assert abs(lhs - rhs) <= 1e-12 * (np.abs(Jd * v).sum() + np.abs(d * JTv).sum())
