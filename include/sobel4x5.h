@@ -26,8 +26,10 @@
  *     SOBEL4X5_EHIP.  sobel4x5_last_error() gives a human-readable detail
  *     for the calling thread's last failed call.
  *   - Inputs and outputs must not overlap (the stencil reads neighbours).
- *   - Calls are thread-safe; a plan must not be launched from two threads at
- *     the same time.
+ *   - Calls are thread-safe.  A plan's work queue admits one launch at a
+ *     time: launches of one plan must be ordered (one stream, or streams
+ *     joined by events), never overlapping.  One-shot batched calls keep a
+ *     separate cached plan per stream, so they may run on several streams.
  *
  * Borders (Sec. 4.3 leaves the padding rule to an earlier work)
  *   SOBEL4X5_BORDER_REPLICATE : clamp-to-edge; output is H x W; any H, W >= 1.
@@ -229,7 +231,10 @@ int sobel4x5_plan_info(sobel4x5_plan plan, int32_t *px_per_lane, int32_t *rows_p
 int sobel4x5_plan_destroy(sobel4x5_plan plan);
 
 /* One-shot batched call: builds (or reuses a cached) plan for these images
- * and launches it on `stream`.  Equivalent to plan_create + plan_launch. */
+ * and launches it on `stream`.  Equivalent to plan_create + plan_launch.
+ * The cache (8 plans, least recently used first out) is keyed by every
+ * descriptor field, the border, the device and the stream; evicting a plan
+ * waits for its stream. */
 int sobel4x5_batched(const sobel4x5_image *imgs, int32_t count, int32_t border, void *stream);
 
 /* Host-only argument check of a batch (never touches the GPU). */
@@ -267,7 +272,10 @@ int sobel4x5_validate_batch_ex(const sobel4x5_image *imgs, const sobel4x5_output
  *   buffers are copied directly, pageable ones through the staging
  *   buffers) with the given border; magnitude only.  Synchronous: returns
  *   when every magnitude is in host memory.  A pipeline must not be run by
- *   two threads at once.
+ *   two threads at once.  On an EHIP return every copy and kernel the call
+ *   queued has finished (nothing writes a caller buffer afterwards), the
+ *   magnitudes of this call's images are unspecified, and the pipeline is
+ *   idle and reusable with any other image array.
  * sobel4x5_pipe_destroy -- wait for nothing, free everything.
  */
 typedef struct sobel4x5_pipe_s *sobel4x5_pipe;
@@ -327,6 +335,16 @@ int sobel4x5_debug_round_mag(const int32_t *S, uint8_t *out, int64_t n, void *st
  * counters.
  */
 int sobel4x5_debug_copy(const void *src, void *dst, int64_t nbytes, void *stream);
+
+/*
+ * Test hook for the error paths: with nth_call = n > 0, the n-th HIP call
+ * made after this one through the library's guarded call sites (the uint8
+ * launch, plan launches, and every copy, launch and wait of
+ * sobel4x5_pipe_run) reports a runtime failure, so the caller gets
+ * SOBEL4X5_EHIP although the call itself ran; 0 disarms.  Process-wide.
+ * EINVAL for n < 0.
+ */
+int sobel4x5_debug_inject_failure(int32_t nth_call);
 
 const char *sobel4x5_status_string(int status);
 const char *sobel4x5_last_error(void);

@@ -153,7 +153,8 @@ static int64_t round_sqrt_i64(int64_t S)
     return (S - r * r > r) ? r + 1 : r;
 }
 
-int64_t oracle_round_sqrt(int64_t S) { return S < 0 ? -1 : round_sqrt_i64(S); }
+/* Exported for tests: -1 outside [0, 2^62), where (r + 1)^2 would leave int64. */
+int64_t oracle_round_sqrt(int64_t S) { return (S < 0 || S >= ((int64_t)1 << 62)) ? -1 : round_sqrt_i64(S); }
 
 /* Output size under a border rule. */
 static int out_dims(int W, int H, int border, int *Wo, int *Ho)

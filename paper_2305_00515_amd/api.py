@@ -85,6 +85,7 @@ def _load() -> ctypes.CDLL:
         "sobel4x5_pipe_destroy": [P],
         "sobel4x5_debug_round_mag": [P, P, I64, P],
         "sobel4x5_debug_copy": [P, P, I64, P],
+        "sobel4x5_debug_inject_failure": [I32],
         "sobel4x5_status_string": [ctypes.c_int],
         "sobel4x5_last_error": [],
         "sobel4x5_version": [],
@@ -459,6 +460,12 @@ def debug_round_mag(S: torch.Tensor) -> torch.Tensor:
     _check(lib.sobel4x5_debug_round_mag(S.data_ptr(), out.data_ptr(), S.numel(), _stream(S)),
            "sobel4x5_debug_round_mag")
     return out
+
+
+def debug_inject_failure(nth_call: int) -> None:
+    """Make the nth_call-th guarded HIP call of the library report a runtime
+    failure (0 disarms); tests of the error paths only."""
+    _check(lib.sobel4x5_debug_inject_failure(int(nth_call)), "sobel4x5_debug_inject_failure")
 
 
 def debug_copy(src: torch.Tensor, dst: torch.Tensor) -> None:

@@ -31,6 +31,17 @@ FLAGS = [
 ]
 
 
+def kernel_hash() -> str:
+    """First 64 bits of a SHA-256 over the kernel sources (*.hip, *.hpp): the
+    autotune cache keys tuned shapes by it."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(CSRC.iterdir()):
+        if f.suffix in (".hip", ".hpp"):
+            h.update(f.name.encode() + b"\0" + f.read_bytes())
+    return "0x" + h.hexdigest()[:16] + "ull"
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):
@@ -60,7 +71,7 @@ def build(verbose: bool = False, out: Path | None = None, defines=()) -> Path:
     out = Path(out) if out else LIB
     objdir = Path(tempfile.mkdtemp(prefix="s4x5_obj_"))
     try:
-        dflags = ["-D" + d for d in defines]
+        dflags = ["-DSOBEL4X5_KERNEL_HASH=" + kernel_hash()] + ["-D" + d for d in defines]
         compile_flags = [f for f in FLAGS if f != "-shared"]
         jobs = []
         for src in SOURCES:

@@ -44,6 +44,21 @@ int hip_fail(hipError_t e, const char *what)
     return fail(SOBEL4X5_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+// Test hook (sobel4x5_debug_inject_failure): while armed with n > 0, the
+// n-th HIP call that passes through guard() reports hipErrorUnknown in place
+// of its own result, which exercises the error paths without a real runtime
+// failure.  The call itself still ran (an enqueued copy is still queued).
+std::atomic<int> g_inject{0};
+
+hipError_t guard(hipError_t e)
+{
+    int n = g_inject.load(std::memory_order_relaxed);
+    while (n > 0) {
+        if (g_inject.compare_exchange_weak(n, n - 1, std::memory_order_relaxed)) return n == 1 ? hipErrorUnknown : e;
+    }
+    return e;
+}
+
 constexpr int64_t kMaxDim = 1 << 30;
 
 // Output size of an operator of radius r (2 for the 5x5 filters, 1 for 3x3).
@@ -510,6 +525,12 @@ std::string tune_cache_path()
     return std::string(home ? home : "/tmp") + "/.cache/sobel4x5_tune.txt";
 }
 
+// Hash of the kernel sources the library was built from (set by the build):
+// a tuned shape is only as good as the code it was timed and checked with.
+#ifndef SOBEL4X5_KERNEL_HASH
+#define SOBEL4X5_KERNEL_HASH 0ull
+#endif
+
 std::string tune_key(const sobel4x5_plan_s *p)
 {
     hipDeviceProp_t prop;
@@ -525,8 +546,9 @@ std::string tune_key(const sobel4x5_plan_s *p)
         px += (int64_t)m.width * m.height;
     }
     char buf[256];
-    std::snprintf(buf, sizeof buf, "v%d|%s|b%d|d%d|n%d|px%lld|h%016llx", SOBEL4X5_VERSION, prop.gcnArchName,
-                  p->border, (int)p->dir, p->count, (long long)px, (unsigned long long)h);
+    std::snprintf(buf, sizeof buf, "v%d|k%016llx|%s|b%d|d%d|n%d|px%lld|h%016llx", SOBEL4X5_VERSION,
+                  (unsigned long long)(SOBEL4X5_KERNEL_HASH), prop.gcnArchName, p->border, (int)p->dir, p->count,
+                  (long long)px, (unsigned long long)h);
     std::string key = buf;
     for (char &c : key)
         if (c == ' ' || c == '\n') c = '_';
@@ -592,19 +614,50 @@ U8Shape batch_default_shape(const std::vector<sobel4x5_image> &imgs, bool dir)
     return s;
 }
 
+// Clear every output plane, so that a candidate that skips pixels cannot
+// reproduce the reference bytes.
+void clear_outputs(const sobel4x5_plan_s *p)
+{
+    for (int32_t i = 0; i < p->count; ++i)
+        for (const Plane &pl : image_planes(p, i)) hipMemset2D(pl.p, pl.pitch, 0xA5, pl.row_bytes, pl.rows);
+}
+
+// Run shape c once on cleared outputs; true when its bytes equal `want`.
+bool candidate_matches(sobel4x5_plan_s *p, const U8Shape &c, const std::vector<uint64_t> &want, int *rc)
+{
+    *rc = SOBEL4X5_OK;
+    if (plan_setup(p, c) != SOBEL4X5_OK) return false;
+    clear_outputs(p);
+    if (plan_direct_launch(p, nullptr) != SOBEL4X5_OK) return false;
+    if (hipDeviceSynchronize() != hipSuccess) {
+        *rc = fail(SOBEL4X5_EHIP, "autotune candidate run failed");
+        return false;
+    }
+    std::vector<uint64_t> got;
+    return batch_fingerprint(p, got) == SOBEL4X5_OK && got == want;   // never trust a mismatch
+}
+
 int plan_autotune(sobel4x5_plan_s *p)
 {
     const std::string key = tune_key(p);
-    U8Shape cached;
-    if (tune_lookup(key, cached)) return plan_setup(p, cached);
 
     // reference bytes with the default shape
     const U8Shape ref = batch_default_shape(p->imgs, p->dir);
     if (int rc = plan_setup(p, ref)) return rc;
     if (int rc = plan_direct_launch(p, nullptr)) return rc;
     if (hipError_t e = hipDeviceSynchronize(); e != hipSuccess) return hip_fail(e, "autotune reference run");
-    std::vector<uint64_t> want, got;
+    std::vector<uint64_t> want;
     if (int rc = batch_fingerprint(p, want)) return rc;
+
+    // a cached shape is used only after it has reproduced the reference
+    // bytes once on these images
+    U8Shape cached;
+    if (tune_lookup(key, cached)) {
+        int rc;
+        if (candidate_matches(p, cached, want, &rc)) return ok();
+        if (rc != SOBEL4X5_OK) return rc;
+        if (int rc2 = plan_setup(p, ref)) return rc2;
+    }
 
     U8Shape best = ref;
     double best_ms = time_plan(p, 10);
@@ -614,13 +667,11 @@ int plan_autotune(sobel4x5_plan_s *p)
         for (int th : ths) {
             const U8Shape c{ppl, th, 4};
             if (c.ppl == ref.ppl && c.th == ref.th && c.waves == ref.waves) continue;
-            if (plan_setup(p, c) != SOBEL4X5_OK) continue;
-            // clear outputs so that a candidate that skips pixels cannot pass
-            for (int32_t i = 0; i < p->count; ++i)
-                for (const Plane &pl : image_planes(p, i)) hipMemset2D(pl.p, pl.pitch, 0xA5, pl.row_bytes, pl.rows);
-            if (plan_direct_launch(p, nullptr) != SOBEL4X5_OK) continue;
-            if (hipDeviceSynchronize() != hipSuccess) return fail(SOBEL4X5_EHIP, "autotune candidate run failed");
-            if (batch_fingerprint(p, got) != SOBEL4X5_OK || got != want) continue;   // never trust a mismatch
+            int rc;
+            if (!candidate_matches(p, c, want, &rc)) {
+                if (rc != SOBEL4X5_OK) return rc;
+                continue;
+            }
             const double ms = time_plan(p, 10);
             if (ms > 0 && ms < best_ms) {
                 best_ms = ms;
@@ -633,9 +684,15 @@ int plan_autotune(sobel4x5_plan_s *p)
 
 // --------------------------------------------------------- one-shot cache
 
+struct CachedPlan {
+    std::string key;
+    sobel4x5_plan plan;
+    hipStream_t stream;   // the only stream this plan is launched on
+};
+
 struct PlanCache {
     std::mutex mu;
-    std::vector<std::pair<std::string, sobel4x5_plan>> lru;   // most recent last
+    std::vector<CachedPlan> lru;   // most recent last
 };
 
 PlanCache &plan_cache()
@@ -644,14 +701,40 @@ PlanCache &plan_cache()
     return *c;
 }
 
+// Key of a one-shot batched call, from the descriptor fields one by one (not
+// the structs' raw bytes, whose padding a C caller may leave uninitialised),
+// the border, the device and the stream.  A plan's work queue admits one
+// launch at a time, so every stream gets plans of its own; launches of one
+// plan on one stream run in order.
 std::string batch_key(const sobel4x5_image *imgs, const sobel4x5_outputs *outs, int32_t count, int32_t border,
-                      int device)
+                      int device, hipStream_t stream)
 {
-    std::string k(reinterpret_cast<const char *>(imgs), sizeof(sobel4x5_image) * (size_t)count);
-    if (outs) k.append(reinterpret_cast<const char *>(outs), sizeof(sobel4x5_outputs) * (size_t)count);
-    k.push_back(outs ? 'o' : 'm');
-    k.append(reinterpret_cast<const char *>(&border), sizeof border);
-    k.append(reinterpret_cast<const char *>(&device), sizeof device);
+    std::string k;
+    auto put = [&](uint64_t v) { k.append(reinterpret_cast<const char *>(&v), sizeof v); };
+    put((uint64_t)(uint32_t)count);
+    put((uint64_t)(uint32_t)border);
+    put((uint64_t)(uint32_t)device);
+    put((uint64_t)reinterpret_cast<uintptr_t>(stream));
+    put(outs ? 1u : 0u);
+    for (int32_t i = 0; i < count; ++i) {
+        const sobel4x5_image &m = imgs[i];
+        put((uint64_t)reinterpret_cast<uintptr_t>(m.src));
+        put(((uint64_t)(uint32_t)m.width << 32) | (uint32_t)m.height);
+        put((uint64_t)m.src_pitch);
+        if (outs) {
+            const sobel4x5_outputs &o = outs[i];
+            put((uint64_t)reinterpret_cast<uintptr_t>(o.mag));
+            put((uint64_t)o.mag_pitch);
+            put((uint64_t)(uint32_t)o.dir_type);
+            if (o.dir_type != SOBEL4X5_DIR_NONE) {
+                for (int d = 0; d < 4; ++d) put((uint64_t)reinterpret_cast<uintptr_t>(o.dir[d]));
+                put((uint64_t)o.dir_pitch);
+            }
+        } else {
+            put((uint64_t)reinterpret_cast<uintptr_t>(m.mag));
+            put((uint64_t)m.mag_pitch);
+        }
+    }
     return k;
 }
 
@@ -753,7 +836,7 @@ int sobel4x5_u8(const uint8_t *src, int32_t width, int32_t height, int64_t src_p
                        out->dir_type ? out->dir : nullptr, out->dir_pitch, out->dir_type);
     const U8Shape s = default_shape(Wo, Ho, out->dir_type);
     u8_tile(j, s);
-    hipError_t e = launch_u8_single(j, border, s, static_cast<hipStream_t>(stream));
+    hipError_t e = guard(launch_u8_single(j, border, s, static_cast<hipStream_t>(stream)));
     return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_u8 launch");
 }
 
@@ -844,7 +927,7 @@ int sobel4x5_plan_launch(sobel4x5_plan plan, void *stream)
     if (!plan || plan->magic != kPlanMagic) return fail(SOBEL4X5_EINVAL, "invalid plan handle");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (plan->use_graph) {
-        hipError_t e = hipGraphLaunch(plan->exec, st);
+        hipError_t e = guard(hipGraphLaunch(plan->exec, st));
         return e == hipSuccess ? ok() : hip_fail(e, "hipGraphLaunch");
     }
     return plan_direct_launch(plan, st);
@@ -876,30 +959,30 @@ int sobel4x5_batched_ex(const sobel4x5_image *imgs, const sobel4x5_outputs *outs
     if (int rc = validate_batch(imgs, outs, count, border)) return rc;
     int dev = 0;
     hipGetDevice(&dev);
-    const std::string key = batch_key(imgs, outs, count, border, dev);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const std::string key = batch_key(imgs, outs, count, border, dev, st);
+    // Lookups, launches and evictions all hold the cache lock, so a plan is
+    // never destroyed between another thread's lookup and its launch.
     PlanCache &c = plan_cache();
-    sobel4x5_plan plan = nullptr;
     {
         std::lock_guard<std::mutex> lk(c.mu);
         for (size_t i = 0; i < c.lru.size(); ++i)
-            if (c.lru[i].first == key) {
-                plan = c.lru[i].second;
-                auto e = c.lru[i];
+            if (c.lru[i].key == key) {
+                CachedPlan e = c.lru[i];
                 c.lru.erase(c.lru.begin() + i);
                 c.lru.push_back(e);
-                break;
+                return sobel4x5_plan_launch(e.plan, stream);
             }
     }
-    if (!plan) {
-        if (int rc = sobel4x5_plan_create_ex(imgs, outs, count, border, 0, &plan)) return rc;
-        std::lock_guard<std::mutex> lk(c.mu);
-        c.lru.emplace_back(key, plan);
-        if (c.lru.size() > 8) {
-            // the evicted plan may still be running on some stream: wait for the device
-            hipDeviceSynchronize();
-            sobel4x5_plan_destroy(c.lru.front().second);
-            c.lru.erase(c.lru.begin());
-        }
+    sobel4x5_plan plan = nullptr;
+    if (int rc = sobel4x5_plan_create_ex(imgs, outs, count, border, 0, &plan)) return rc;
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.lru.push_back(CachedPlan{key, plan, st});
+    if (c.lru.size() > 8) {
+        const CachedPlan evicted = c.lru.front();
+        c.lru.erase(c.lru.begin());
+        (void)hipStreamSynchronize(evicted.stream);   // it may still be running there
+        sobel4x5_plan_destroy(evicted.plan);
     }
     return sobel4x5_plan_launch(plan, stream);
 }
@@ -1069,6 +1152,13 @@ int sobel4x5_u8_weighted(const uint8_t *src, int32_t width, int32_t height, int6
     return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_u8_weighted launch");
 }
 
+int sobel4x5_debug_inject_failure(int32_t nth_call)
+{
+    if (nth_call < 0) return fail(SOBEL4X5_EINVAL, "nth_call must be >= 0");
+    g_inject.store(nth_call, std::memory_order_relaxed);
+    return ok();
+}
+
 int sobel4x5_debug_copy(const void *src, void *dst, int64_t nbytes, void *stream)
 {
     if (nbytes < 0 || (nbytes % 16) || (nbytes > 0 && (!src || !dst)) ||
@@ -1130,15 +1220,31 @@ int sobel4x5_pipe_run(sobel4x5_pipe p, const sobel4x5_image *imgs, int32_t count
         if (int rc = check_pitch("mag", m.mag_pitch, Wo, Ho)) return rc;
     }
     const int depth = (int)p->slots.size();
+    // A slot's `pending` indexes THIS call's image array.  Every return path
+    // leaves every slot idle: on an error, wait for whatever the slots still
+    // have queued (a copy into a caller's pinned buffer must not land after
+    // the return) and drop the pending images without copying them out, so
+    // that a later call, with another array, never finishes an image of
+    // this one.
+    auto abandon = [&](int rc) {
+        for (auto &sl : p->slots) {
+            if (sl.st) (void)hipStreamSynchronize(sl.st);
+            sl.pending = -1;
+            sl.staged_out = false;
+        }
+        return rc;
+    };
+    for (auto &sl : p->slots)   // idle after every earlier call; keep it so
+        if (sl.pending >= 0) abandon(SOBEL4X5_OK);
     auto drain = [&](PipeSlot &sl) -> hipError_t {
         if (sl.pending < 0) return hipSuccess;
-        hipError_t e = hipStreamSynchronize(sl.st);
+        hipError_t e = guard(hipStreamSynchronize(sl.st));
         if (e == hipSuccess) pipe_finish(sl, imgs, border);
         return e;
     };
     for (int32_t i = 0; i < count; ++i) {
         PipeSlot &sl = p->slots[i % depth];
-        if (hipError_t e = drain(sl); e != hipSuccess) return hip_fail(e, "pipeline wait");
+        if (hipError_t e = drain(sl); e != hipSuccess) return abandon(hip_fail(e, "pipeline wait"));
         const sobel4x5_image &m = imgs[i];
         int32_t Wo, Ho;
         out_dims(m.width, m.height, border, &Wo, &Ho);
@@ -1152,20 +1258,24 @@ int sobel4x5_pipe_run(sobel4x5_pipe p, const sobel4x5_image *imgs, int32_t count
             hs = sl.h_src;
             hp = sl.pitch;
         }
-        hipError_t e = hipMemcpy2DAsync(sl.d_src, sl.pitch, hs, hp, m.width, m.height, hipMemcpyHostToDevice, sl.st);
-        if (e != hipSuccess) return hip_fail(e, "pipeline host-to-device copy");
+        // the slot owns image i from its first enqueued operation on
+        sl.pending = i;
+        sl.staged_out = false;
+        hipError_t e = guard(
+            hipMemcpy2DAsync(sl.d_src, sl.pitch, hs, hp, m.width, m.height, hipMemcpyHostToDevice, sl.st));
+        if (e != hipSuccess) return abandon(hip_fail(e, "pipeline host-to-device copy"));
         U8Job j = make_job(sl.d_src, m.width, m.height, sl.pitch, Wo, Ho, sl.d_mag, sl.pitch, nullptr, 0, 0);
         const U8Shape shape = default_shape(Wo, Ho, SOBEL4X5_DIR_NONE);
         u8_tile(j, shape);
-        if ((e = launch_u8_single(j, border, shape, sl.st)) != hipSuccess) return hip_fail(e, "pipeline launch");
+        if ((e = guard(launch_u8_single(j, border, shape, sl.st))) != hipSuccess)
+            return abandon(hip_fail(e, "pipeline launch"));
         sl.staged_out = !is_pinned(m.mag);
-        e = hipMemcpy2DAsync(sl.staged_out ? sl.h_mag : m.mag, sl.staged_out ? sl.pitch : m.mag_pitch, sl.d_mag,
-                             sl.pitch, Wo, Ho, hipMemcpyDeviceToHost, sl.st);
-        if (e != hipSuccess) return hip_fail(e, "pipeline device-to-host copy");
-        sl.pending = i;
+        e = guard(hipMemcpy2DAsync(sl.staged_out ? sl.h_mag : m.mag, sl.staged_out ? sl.pitch : m.mag_pitch,
+                                   sl.d_mag, sl.pitch, Wo, Ho, hipMemcpyDeviceToHost, sl.st));
+        if (e != hipSuccess) return abandon(hip_fail(e, "pipeline device-to-host copy"));
     }
     for (auto &sl : p->slots)
-        if (hipError_t e = drain(sl); e != hipSuccess) return hip_fail(e, "pipeline wait");
+        if (hipError_t e = drain(sl); e != hipSuccess) return abandon(hip_fail(e, "pipeline wait"));
     return ok();
 }
 

@@ -283,8 +283,27 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
     if (X1 <= X0) return;
     const int lane = threadIdx.x & 63;
     const int c = s * kOwnB - kHaloB + 2 * lane;             // input column of element a
-    const bool in_lane = lane >= kHaloB / 2 && lane < (kHaloB + kOwnB) / 2;
-    const bool keep_a = in_lane && c < a.W, keep_b = in_lane && c + 1 < a.W;
+    // replicate: fold the padded columns -2, -1 onto 0 and W, W+1 onto W-1;
+    // reflect-101: -1, -2 onto 1, 2 and W, W+1 onto W-2, W-3 (as the
+    // index rule maps them for narrow images).  Wave-uniform: does this
+    // strip hold column 0 / W-1?
+    constexpr bool kFold = OFF == 0 && BM != kZero;
+    const bool fold_l = kFold && s == 0;
+    const bool fold_r = kFold && s * kOwnB + kOwnB >= a.W;
+    // Columns this wave stores, [klo, khi): its own 116, except under
+    // reflect-101, where the last strip (the only one whose lanes hold the
+    // adjoint at the padded columns W and W+1) also takes W-3 and W-2, the
+    // mirrors of those columns, and the strip before gives them up.  The
+    // adjoint is complete on lanes 2..61 (columns s*116-2 .. s*116+117), and
+    // W-3 >= s*116-2 holds for the last strip.
+    int klo = s * kOwnB, khi = min(s * kOwnB + kOwnB, a.W);
+    if constexpr (kFold && BM == kRefl) {
+        if (fold_r)
+            klo = max(0, min(klo, a.W - 3));
+        else
+            khi = min(khi, max(0, a.W - 3));
+    }
+    const bool keep_a = c >= klo && c < khi, keep_b = c + 1 >= klo && c + 1 < khi;
     // an output pixel is centred on the column
     const bool oc_a = c - OFF >= 0 && c - OFF < a.Wo, oc_b = c + 1 - OFF >= 0 && c + 1 - OFF < a.Wo;
     const int64_t xa = (int64_t)edge_index<BM>(c, a.W) * 4, xb = (int64_t)edge_index<BM>(c + 1, a.W) * 4;
@@ -293,13 +312,6 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
     const char *src = reinterpret_cast<const char *>(a.src) + (int64_t)b * a.src_bstride;
     const char *gr = reinterpret_cast<const char *>(a.grad) + (int64_t)b * a.g_bstride;
     char *dst = reinterpret_cast<char *>(a.out) + (int64_t)b * a.out_bstride + (int64_t)(c < 0 ? 0 : c) * 4;
-    // replicate: fold the padded columns -2, -1 onto 0 and W, W+1 onto W-1;
-    // reflect-101: -1, -2 onto 1, 2 and W, W+1 onto W-2, W-3 (as the
-    // index rule maps them for narrow images).  Wave-uniform: does this
-    // strip hold column 0 / W-1?
-    constexpr bool kFold = OFF == 0 && BM != kZero;
-    const bool fold_l = kFold && s == 0;
-    const bool fold_r = kFold && s * kOwnB + kOwnB >= a.W;
     const int c0 = s * kOwnB - kHaloB;                        // column of lane 0's element a
     // input rows X0-4 .. X1+3 give the adjoint rows [X0, X1); at the top and
     // bottom of the image, where padded rows fold back, two more rows on

@@ -41,10 +41,15 @@ def check_bwd(oracle_mod, x, g, dx, border):
 
 @pytest.mark.parametrize("border", [0, 1, 2, 3])
 @pytest.mark.parametrize("shape", [(1, 5, 5), (2, 37, 45), (1, 64, 64), (3, 100, 33), (1, 1, 9), (1, 7, 1),
-                                   (1, 2, 3), (2, 3, 4), (1, 300, 130), (1, 70, 260)])
+                                   (1, 2, 3), (2, 3, 4), (1, 300, 130), (1, 70, 260),
+                                   (1, 12, 116), (1, 12, 117), (1, 10, 118), (1, 9, 119), (2, 9, 233),
+                                   (1, 8, 234), (1, 7, 232)])
 def test_forward_backward_small(oracle_mod, sobel_lib, gpu, border, shape):
     """Every border rule, on shapes that span several column strips and row
-    chunks (130, 260 columns; 300 rows) and on images so small that the
+    chunks (130, 260 columns; 300 rows), on widths around a multiple of the
+    adjoint's 116-column strips (W mod 116 in {0, 1, 2, 3}: under
+    REFLECT101 the mirrors W-2, W-3 of the padded columns W, W+1 then lie in
+    the strip before the last one), and on images so small that the
     reflection repeats (1 to 4 rows or columns)."""
     b, h, w = shape
     if border == 1 and min(h, w) < 5:
@@ -107,7 +112,8 @@ def test_config4_fd_and_oracle_gradient(oracle_mod, sobel_lib, gpu):
     """32 x 1024^2, loss = mean(M): the GPU gradient at 64 random pixels (8 on
     the border) against central differences of the fp64 oracle (local: only
     the 5x5 outputs around the pixel change), Richardson-extrapolated from
-    h = 1e-3; and the whole gradient of image 0 against the oracle's."""
+    h = 1e-3; and the whole forward and gradient of all 32 images against the
+    oracle's."""
     from paper_2305_00515_amd import sobel4x5_magnitude
     B, H, W = 32, 1024, 1024
     x = f32_batch(B, H, W, 2000)
@@ -146,6 +152,10 @@ def test_config4_fd_and_oracle_gradient(oracle_mod, sobel_lib, gpu):
         g1[0, oy0 - y0:oy1 - y0, ox0 - x0:ox1 - x0] = 1.0 / n
         A = oracle_mod.sobel_f64_bwd_scale(patch[None], g1)[0, py - y0, px - x0]
         assert abs(grad[b, py, px] - rich) <= TOL * A + 1e-14, (b, py, px, grad[b, py, px], rich, A)
-    # the oracle's gradient of the first image (the batch images are independent)
-    g = np.full((1, H, W), 1.0 / n)
-    check_bwd(oracle_mod, x[:1], g.astype(np.float32), grad[:1], 0)
+    # the whole forward and the whole gradient of every image against the
+    # oracle, at the scaled tolerances
+    M = sobel_lib.sobel4x5_f32_fwd(xt.detach())
+    torch.cuda.synchronize()
+    check_fwd(oracle_mod, x, M.cpu().numpy(), 0)
+    g = np.full((B, H, W), 1.0 / n, np.float32)
+    check_bwd(oracle_mod, x, g, grad, 0)

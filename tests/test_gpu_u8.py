@@ -64,18 +64,16 @@ def test_low_amplitude_images_exercise_rounding(oracle_mod, sobel_lib, gpu):
         assert np.array_equal(mag, om)
 
 
-# The 63 x 64 case faulted the GPU through an out-of-bounds halo load of
-# idle 16-lane groups (lane 0 loaded column xo - 4 with xo far past the row
-# end).  The cause is fixed (csrc/load_columns.hpp) and checked on the host
-# for every lane of every launch geometry (test_load_columns.py); the case
-# itself stays off the GPU until a later session re-enables it.
-FAULTED_63x64 = pytest.mark.skip(reason="faulted the GPU before the halo-load clamp fix; "
-                                        "re-enable once the fix has run clean on the GPU")
+# 63 x 64 faulted the GPU once, through an out-of-bounds halo load of idle
+# 16-lane groups (lane 0 loaded column xo - 4 with xo far past the row end).
+# The cause is fixed (csrc/load_columns.hpp clamps every load column) and
+# checked on the host for every lane of every launch geometry
+# (test_load_columns.py); the case runs here again as the fix's GPU check.
 
 
 @pytest.mark.parametrize("h,w", [(1, 1), (1, 2), (2, 1), (3, 3), (4, 7), (5, 5), (6, 17),
                                  (7, 15), (15, 16), (16, 17), (17, 63),
-                                 pytest.param(63, 64, marks=FAULTED_63x64), (64, 65),
+                                 (63, 64), (64, 65),
                                  (65, 127), (127, 128), (129, 255), (33, 256), (20, 257),
                                  (40, 1000), (9, 1920), (300, 4099)])
 def test_size_sweep(oracle_mod, sobel_lib, gpu, h, w):
@@ -125,36 +123,49 @@ def test_config1_field_images(oracle_mod, sobel_lib, gpu, hw):
     assert np.array_equal(mag, om)
 
 
+def oracle_bands(img, band=2048, border=0, want_mag=True, want_dir=False):
+    """Oracle outputs of a large image, computed in row bands so that host
+    memory stays bounded: band [y0, y1) takes input rows [y0-2, y1+2)
+    clipped to the image, which holds every row its outputs read (at the top
+    and bottom the clip is the image edge itself, where REPLICATE clamps
+    anyway)."""
+    import oracle
+    h = img.shape[0]
+    for y0 in range(0, h, band):
+        y1 = min(h, y0 + band)
+        a, b = max(0, y0 - 2), min(h, y1 + 2)
+        m, d = oracle.sobel_u8(img[a:b], border, want_mag=want_mag, want_dir=want_dir)
+        yield y0, y1, (None if m is None else m[y0 - a:y1 - a]), (None if d is None else d[:, y0 - a:y1 - a])
+
+
+def test_oracle_bands_equal_whole_image(oracle_mod):
+    img = synth.rect_image(70, 90, 12)
+    om, od = oracle_mod.sobel_u8(img)
+    for y0, y1, m, d in oracle_bands(img, band=16, want_dir=True):
+        assert np.array_equal(m, om[y0:y1]) and np.array_equal(d, od[:, y0:y1])
+
+
 @pytest.mark.parametrize("n", [4096, 8192, 16384])
-def test_config2_large_sampled(oracle_mod, sobel_lib, gpu, n):
-    """Full-size images, magnitude-only launch (the benchmarked one): every
-    tile border row/column plus random pixels against the oracle point by
-    point, and the transposed image gives the transposed magnitude."""
+def test_config2_full_image(oracle_mod, sobel_lib, gpu, n):
+    """Full-size images against the oracle, every pixel: the magnitude-only
+    launch (the benchmarked one) and the four int16 directional planes."""
     img = synth.rect_image(n, n, 3)
     src = dev_image(img, gpu)
     mag = sobel_lib.sobel4x5_u8(src)[0]
     torch.cuda.synchronize()
     m = mag.cpu().numpy()
-    rng = np.random.default_rng(n)
-    ys = np.concatenate([rng.integers(0, n, 20000), np.arange(n), np.arange(n), np.zeros(n, int),
-                         np.full(n, n - 1)])
-    xs = np.concatenate([rng.integers(0, n, 20000), np.zeros(n, int), np.full(n, n - 1), np.arange(n),
-                         np.arange(n)])
-    # tile boundaries: columns k*256 - 1, k*256 and rows at multiples of 8
-    cols = np.concatenate([np.arange(0, n, 256), np.arange(255, n, 256)])
-    rows = rng.integers(0, n, cols.size)
-    ys = np.concatenate([ys, rows, (np.arange(cols.size) * 8) % n])
-    xs = np.concatenate([xs, cols, cols])
-    om, _ = oracle_mod.sobel_u8_points(img, ys, xs)
-    assert np.array_equal(m[ys, xs], om)
-    del src, mag
-    # directional int16 planes on a band, checked point-wise too
-    if n <= 8192:
-        _, dirs = sobel_lib.sobel4x5_u8(dev_image(img, gpu), want_mag=False, dir_type=1)
-        torch.cuda.synchronize()
-        d = np.stack([t.cpu().numpy()[ys, xs] for t in dirs], axis=1)
-        _, od = oracle_mod.sobel_u8_points(img, ys, xs)
-        assert np.array_equal(d.astype(np.int32), od)
+    del mag
+    for y0, y1, om, _ in oracle_bands(img):
+        bad = int((m[y0:y1] != om).sum())
+        assert bad == 0, "magnitude rows %d..%d: %d pixels differ" % (y0, y1, bad)
+    del m
+    _, dirs = sobel_lib.sobel4x5_u8(src, want_mag=False, dir_type=1)
+    torch.cuda.synchronize()
+    for y0, y1, _, od in oracle_bands(img, want_mag=False, want_dir=True):
+        for k in range(4):
+            got = dirs[k][y0:y1].cpu().numpy().astype(np.int32)
+            bad = int((got != od[k]).sum())
+            assert bad == 0, "plane %d rows %d..%d: %d values differ" % (k, y0, y1, bad)
 
 
 def test_transpose_property_full_size(sobel_lib, gpu):
