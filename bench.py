@@ -27,13 +27,6 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 # lane operations per second (one VALU instruction of a wave64 occupies a SIMD
 # for 4 cycles).  Packed int16 instructions count once: they are one issue.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# VALU issue slots per output pixel of the magnitude-only interior path: the
-# 5-row loop body of k_u8_single<16, replicate, aligned, mag-only>, which makes
-# 5 rows x 16 pixels per lane, holds 1791 VALU instructions (counted in its
-# ISA), 80 of them v_sqrt_f32, which issues at half rate (measured: 8.5 cycles
-# per wave instruction against 4.5 for v_fma_f32) and so takes two slots.
-U8_VALU_INSTR_PER_PX = 1791 / 80.0
-U8_VALU_OPS_PER_PX = (1791 + 80) / 80.0
 N = 8192
 ROTATE_BYTES = 2 << 30         # >= 1 GiB of distinct buffers (Infinity Cache is 256 MB)
 
@@ -61,20 +54,43 @@ def parse():
     return a
 
 
-def time_launches(torch, fn, steps, warmup):
-    """Average ms per call of fn(i) over `steps` calls, HIP events on the current stream."""
+def time_launches(torch, fn, steps, warmup, first=0):
+    """Average ms per call of fn(i) over `steps` calls (i counting from
+    `first`), HIP events on the current stream, which is the stream the
+    library's calls enqueue on."""
     for i in range(warmup):
-        fn(i)
+        fn(first + i)
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for i in range(steps):
-        fn(i)
+        fn(first + warmup + i)
     e1.record(s)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def clock_warmup(torch, fn, min_s=1.0, max_s=8.0, batch=50, tol=0.02):
+    """Launch fn(i) in timed batches until the GPU clocks have settled: at
+    least min_s seconds, and the last three batch averages within `tol` of
+    each other (at most max_s seconds).  The first few hundred launches of a
+    process run at ramp-up clocks; a fixed small --warmup would time those.
+    Returns the number of launches made."""
+    t0 = time.perf_counter()
+    hist, n = [], 0
+    while True:
+        hist.append(time_launches(torch, fn, batch, 0, first=n))
+        n += batch
+        el = time.perf_counter() - t0
+        if el >= max_s:
+            break
+        if el >= min_s and len(hist) >= 3 and max(hist[-3:]) <= (1 + tol) * min(hist[-3:]):
+            break
+    log("clock warm-up: %d launches in %.2f s; batch averages (ms) first %s, last %s" % (
+        n, time.perf_counter() - t0, ["%.4f" % h for h in hist[:3]], ["%.4f" % h for h in hist[-3:]]))
+    return n
 
 
 def warm(torch, fn, n):
@@ -119,12 +135,13 @@ def bench_u8(torch, api, synth, dev, steps, warmup):
         k = i % nsets
         api.sobel4x5_u8(srcs[k], mag=mags[k])
 
-    ms = time_launches(torch, step, steps, warmup)
+    nclock = clock_warmup(torch, step)
+    ms = time_launches(torch, step, steps, warmup, first=nclock)
     per = per_launch_us(torch, step, 50)
     hot = time_launches(torch, lambda i: api.sobel4x5_u8(srcs[0], mag=mags[0]), steps, warmup)
     px = N * N
     res = {
-        "ms": ms, "gpx": px / (ms * 1e-3) / 1e9, "alg_bytes": 2 * px,
+        "ms": ms, "gpx": px / (ms * 1e-3) / 1e9, "alg_bytes": 2 * px, "clock_warmup_launches": nclock,
         "hot_ms": hot, "nsets": nsets, "rotating_gib": nsets * 2 * px / 2 ** 30, "per_launch_us": per,
     }
     del srcs, mags
@@ -407,11 +424,16 @@ def bench_copy(torch, api, dev, steps):
     return {"bytes_moved": 2 * n, "ms": round(ms, 4), "GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
-# HBM bytes per launch of the headline kernel from rocprofv3 --pmc FETCH_SIZE
-# and WRITE_SIZE (KiB per dispatch), scaled by what the same counters read for
-# the plain copy kernel (sobel4x5_debug_copy) of known size.  Valid only for
-# the kernel source they were taken on (its SHA-256 prefix); None otherwise.
-U8_TRAFFIC = {"src_sha256": "f32f9ced96bc6bdf", "bytes": 145204014}   # profiles/k_u8_single_8192x8192_mag_u8.md
+# Per-launch figures of the headline kernel read off its profile and its ISA,
+# valid only for the kernel source they were taken on (the SHA-256 prefix of
+# U8_KERNEL_SOURCES); reported as null for any other source.
+#   traffic: HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and
+#            WRITE_SIZE (KiB per dispatch), each scaled by what the same
+#            counter reads for the plain copy kernel (sobel4x5_debug_copy) of
+#            known size (profiles/k_u8_single_8192x8192_mag_u8.md);
+#   valu:    VALU issue slots per output pixel (SQ_INSTS_VALU per pixel from
+#            the same profile, counting the half-rate square root twice).
+U8_PROFILE = {"src_sha256": "f32f9ced96bc6bdf", "traffic_bytes": 145204014, "valu_slots_per_px": (1791 + 80) / 80.0}
 
 
 # Sources k_u8_single is compiled from (the hash covers them in this order);
@@ -431,8 +453,8 @@ def u8_source_hash():
     return h.hexdigest()[:16]
 
 
-def u8_traffic():
-    return U8_TRAFFIC["bytes"] if u8_source_hash() == U8_TRAFFIC["src_sha256"] else None
+def u8_profile(key):
+    return U8_PROFILE[key] if u8_source_hash() == U8_PROFILE["src_sha256"] else None
 
 
 def cpu_baseline(img):
@@ -500,23 +522,28 @@ def main():
     if want("u8"):
         log("u8 8192x8192 magnitude: %d steps" % args.steps)
         r, img = bench_u8(torch, api, synth, dev, args.steps, args.warmup)
+        # the dominant (and only) kernel of a step: algorithmic bytes per
+        # launch (1 byte read + 1 written per pixel) over its average launch
+        # time from the HIP events around the timed launches
         gbs = r["alg_bytes"] / (r["ms"] * 1e-3) / 1e9
-        tops = U8_VALU_OPS_PER_PX * N * N / (r["ms"] * 1e-3) / 1e12
+        slots = u8_profile("valu_slots_per_px")
+        valu = None
+        if slots is not None:
+            tops = slots * N * N / (r["ms"] * 1e-3) / 1e12
+            valu = {"slots_per_px": round(slots, 3), "achieved_TOPs": round(tops, 2),
+                    "peak_TOPs": round(VALU_PEAK_TOPS, 2), "issue_frac": round(tops / VALU_PEAK_TOPS, 4)}
         line.update({
             "value": round(r["gpx"], 2), "ms_per_step": round(r["ms"], 5),
             "config": {"workload": "uint8 8192x8192 four-directional 5x5 Sobel, uint8 magnitude only, "
                                    "replicate border, one image per step",
                        "image": "rect_image(8192, 8192, seed=3): uniform noise + 20 filled rectangles",
                        "bytes_per_px": 2, "rotating_buffers_gib": round(r["rotating_gib"], 2),
+                       "clock_warmup_launches": r["clock_warmup_launches"],
                        "hot_same_buffer_ms": round(r["hot_ms"], 5), "per_launch_us": r["per_launch_us"]},
-            "roofline": {"bound": "alu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
-                         "unit": "TOP/s", "frac": round(tops / VALU_PEAK_TOPS, 4),
-                         "traffic": u8_traffic(),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": u8_profile("traffic_bytes"),
                          "kernel": "k_u8_single<16,replicate,aligned,mag-only>",
-                         "valu_slots_per_px": round(U8_VALU_OPS_PER_PX, 3),
-                         "valu_instr_per_px": round(U8_VALU_INSTR_PER_PX, 3),
-                         "alg_bytes_per_launch": r["alg_bytes"], "hbm_GBps": round(gbs, 1),
-                         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)},
+                         "alg_bytes_per_launch": r["alg_bytes"], "valu": valu},
         })
     if want("copy"):
         log("copy ceiling")

@@ -328,6 +328,17 @@ int sobel4x5_validate_f32(const float *src, int32_t batch, int32_t width, int32_
 int sobel4x5_debug_round_mag(const int32_t *S, uint8_t *out, int64_t n, void *stream);
 
 /*
+ * The same with a choice of the library's two implementations of that
+ * rounding: method 0 converts S to fp32 and rounds its square root (the
+ * kernels that run three waves per SIMD); method 1 reads a table of the
+ * rounded value of every S below 2^16, held in LDS, at min(S, 65535) (the
+ * kernels that run two waves per SIMD, the 8192^2 magnitude kernel among
+ * them).  Both must give the same byte for every S.  EINVAL for another
+ * method.
+ */
+int sobel4x5_debug_round_mag_ex(const int32_t *S, uint8_t *out, int64_t n, int32_t method, void *stream);
+
+/*
  * Diagnostic: plain device-to-device copy of nbytes (a multiple of 16;
  * 16-byte aligned device pointers) with 128-bit accesses, each workgroup
  * copying one contiguous 16 KiB block.  It is the measured reference for

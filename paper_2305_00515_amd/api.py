@@ -84,6 +84,7 @@ def _load() -> ctypes.CDLL:
         "sobel4x5_pipe_run": [P, ctypes.POINTER(Image), I32, I32],
         "sobel4x5_pipe_destroy": [P],
         "sobel4x5_debug_round_mag": [P, P, I64, P],
+        "sobel4x5_debug_round_mag_ex": [P, P, I64, I32, P],
         "sobel4x5_debug_copy": [P, P, I64, P],
         "sobel4x5_debug_inject_failure": [I32],
         "sobel4x5_status_string": [ctypes.c_int],
@@ -452,13 +453,14 @@ def sobel4x5_f32_bwd(x: torch.Tensor, grad_mag: torch.Tensor, border: int = BORD
     return out if x.dim() == 3 else out.view(h, w)
 
 
-def debug_round_mag(S: torch.Tensor) -> torch.Tensor:
-    """The library's uint8 rounding min(255, round(sqrt(S))) of int32 values S."""
+def debug_round_mag(S: torch.Tensor, method: int = 0) -> torch.Tensor:
+    """The library's uint8 rounding min(255, round(sqrt(S))) of int32 values
+    S: method 0 by the fp32 square root, 1 by the LDS table."""
     _need_cuda(S, torch.int32, "S")
     S = S.contiguous()
     out = torch.empty(S.shape, dtype=torch.uint8, device=S.device)
-    _check(lib.sobel4x5_debug_round_mag(S.data_ptr(), out.data_ptr(), S.numel(), _stream(S)),
-           "sobel4x5_debug_round_mag")
+    _check(lib.sobel4x5_debug_round_mag_ex(S.data_ptr(), out.data_ptr(), S.numel(), int(method), _stream(S)),
+           "sobel4x5_debug_round_mag_ex")
     return out
 
 

@@ -106,7 +106,8 @@ hipError_t launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t st
 int64_t fingerprint_blocks(int64_t rows);
 hipError_t launch_fingerprint(const void *base, int64_t pitch, int64_t row_bytes, int64_t rows, uint64_t *partials,
                               hipStream_t stream);
-hipError_t launch_round_mag(const int32_t *S, uint8_t *out, int64_t n, hipStream_t stream);
+// method 0: the square-root rounding; 1: the LDS table (u8_sweep.hpp)
+hipError_t launch_round_mag(const int32_t *S, uint8_t *out, int64_t n, int method, hipStream_t stream);
 
 // fp32 path (pointers and strides as in the public header).
 struct F32Args {

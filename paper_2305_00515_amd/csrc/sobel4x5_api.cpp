@@ -1168,11 +1168,17 @@ int sobel4x5_debug_copy(const void *src, void *dst, int64_t nbytes, void *stream
     return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_debug_copy launch");
 }
 
-int sobel4x5_debug_round_mag(const int32_t *S, uint8_t *out, int64_t n, void *stream)
+int sobel4x5_debug_round_mag_ex(const int32_t *S, uint8_t *out, int64_t n, int32_t method, void *stream)
 {
     if (n < 0 || (n > 0 && (!S || !out))) return fail(SOBEL4X5_EINVAL, "bad arguments");
-    hipError_t e = launch_round_mag(S, out, n, static_cast<hipStream_t>(stream));
+    if (method != 0 && method != 1) return fail(SOBEL4X5_EINVAL, "method must be 0 or 1, got %d", method);
+    hipError_t e = launch_round_mag(S, out, n, method, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_debug_round_mag launch");
+}
+
+int sobel4x5_debug_round_mag(const int32_t *S, uint8_t *out, int64_t n, void *stream)
+{
+    return sobel4x5_debug_round_mag_ex(S, out, n, 0, stream);
 }
 
 int sobel4x5_pipe_create(int32_t max_width, int32_t max_height, int32_t depth, sobel4x5_pipe *out)

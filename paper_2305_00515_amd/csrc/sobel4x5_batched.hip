@@ -57,6 +57,13 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
                                                             uint32_t *queue, int TH)
 {
     constexpr int TW = 16 * PPL;
+    constexpr bool LUT = use_lut(single_waves(PPL, kOp4x5, ALIGNED, DIR));
+    __shared__ __attribute__((aligned(16))) uint8_t lut[LUT ? kLutSize : 16];
+    if constexpr (LUT) {
+        lut_fill<64 * kWaves>(lut);
+        __syncthreads();
+    }
+    lds_u8 *lutp = (lds_u8 *)lut;
     const int lane = threadIdx.x & 63;
     // one tile of the table: returns false when it has no rows
     auto run_tile = [&](int t) __attribute__((always_inline)) {
@@ -76,11 +83,11 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
             fast = ALIGNED && full && (ti.z + 1) * TW <= J.Wo;
         }
         if (fast && !g.fix_right && !g.fix_left)
-            sweep<PPL, OFF, ALIGNED, DIR, true, false, kOp4x5, BM, false>(J, g);
+            sweep<PPL, OFF, ALIGNED, DIR, true, false, kOp4x5, BM, LUT, false>(J, g, lutp);
         else if (fast)
-            sweep<PPL, OFF, ALIGNED, DIR, true, true, kOp4x5, BM, false>(J, g);
+            sweep<PPL, OFF, ALIGNED, DIR, true, true, kOp4x5, BM, LUT, false>(J, g, lutp);
         else
-            sweep<PPL, OFF, ALIGNED, DIR, false, false, kOp4x5, BM, false>(J, g);
+            sweep<PPL, OFF, ALIGNED, DIR, false, false, kOp4x5, BM, LUT, false>(J, g, lutp);
     };
     if (queue == nullptr) {
         // static form: wave w of the grid takes tile w, no queue

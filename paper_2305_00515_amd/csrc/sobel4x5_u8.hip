@@ -63,6 +63,17 @@ __global__ void k_round_mag(const int32_t *S, uint8_t *out, int64_t n)
     if (i < n) out[i] = (uint8_t)round_mag(S[i]);
 }
 
+// The same rounding through the LDS table, filled and read exactly as the
+// sweep does.
+__global__ __launch_bounds__(256) void k_round_mag_lut(const int32_t *S, uint8_t *out, int64_t n)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t lut[kLutSize];
+    lut_fill<256>(lut);
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (uint8_t)lut_mag((lds_u8 *)lut, S[i]);
+}
+
 }  // namespace
 
 bool u8_rows_aligned(const U8Job &j)
@@ -109,11 +120,15 @@ hipError_t launch_fingerprint(const void *base, int64_t pitch, int64_t row_bytes
     return hipGetLastError();
 }
 
-hipError_t launch_round_mag(const int32_t *S, uint8_t *out, int64_t n, hipStream_t st)
+hipError_t launch_round_mag(const int32_t *S, uint8_t *out, int64_t n, int method, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(k_round_mag, dim3((unsigned)blocks), dim3(256), 0, st, S, out, n);
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    if (method == 1)
+        hipLaunchKernelGGL(k_round_mag_lut, dim3((unsigned)blocks), dim3(256), 0, st, S, out, n);
+    else
+        hipLaunchKernelGGL(k_round_mag, dim3((unsigned)blocks), dim3(256), 0, st, S, out, n);
     return hipGetLastError();
 }
 

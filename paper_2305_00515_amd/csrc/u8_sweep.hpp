@@ -111,6 +111,59 @@ __device__ __forceinline__ u32 round_mag(int S)
     return __builtin_amdgcn_cvt_pk_u8_f32(mag_f(S), 0, 0u);
 }
 
+// Rounded uint8 magnitude of every S below 2^16, the same function as
+// round_mag: k for k^2 - k < S <= k^2 + k (the S whose square root rounds to
+// k; ties cannot occur), 0 for S = 0, 255 from 255^2 + 256 = 65281 on.  It
+// is built at compile time into device memory; a kernel that rounds through
+// it copies it into LDS once per workgroup and then rounds a pixel with one
+// clamp (min(S, 65535)) and one LDS byte read instead of a conversion, a
+// half-rate square root and a pack.
+constexpr int kLutSize = 1 << 16;
+struct MagLut {
+    uint8_t v[kLutSize];
+};
+constexpr MagLut make_mag_lut()
+{
+    MagLut t{};
+    int S = 1;
+    for (int k = 1; k <= 255; ++k)
+        for (const int hi = k * k + k; S <= hi && S < kLutSize; ++S) t.v[S] = (uint8_t)k;
+    for (; S < kLutSize; ++S) t.v[S] = 255;
+    return t;
+}
+constexpr MagLut kMagLut = make_mag_lut();
+static_assert(kMagLut.v[0] == 0 && kMagLut.v[1] == 1 && kMagLut.v[2] == 1 && kMagLut.v[3] == 2 &&
+                  kMagLut.v[1088] == 33 && kMagLut.v[64770] == 254 && kMagLut.v[64771] == 255 &&
+                  kMagLut.v[kLutSize - 1] == 255,
+              "rounding table");
+
+typedef const uint8_t __attribute__((address_space(3))) lds_u8;
+
+// Copy the table into LDS (`threads` threads of the workgroup, 16 bytes per
+// load; every load is issued before the first store).  The caller
+// synchronises the workgroup before the first read.
+template <int THREADS>
+__device__ __forceinline__ void lut_fill(uint8_t *lut)
+{
+    static_assert(kLutSize % (16 * THREADS) == 0, "table split");
+    constexpr int kPer = kLutSize / (16 * THREADS);
+    uint4 v[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) v[k] = reinterpret_cast<const uint4 *>(kMagLut.v)[threadIdx.x + k * THREADS];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) reinterpret_cast<uint4 *>(lut)[threadIdx.x + k * THREADS] = v[k];
+}
+
+__device__ __forceinline__ u32 lut_mag(lds_u8 *lut, int S) { return lut[min((u32)S, (u32)kLutSize - 1u)]; }
+
+// (a << s) | b in one v_lshl_or_b32
+__device__ __forceinline__ u32 lshl_or(u32 a, int s, u32 b)
+{
+    u32 r;
+    asm("v_lshl_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "i"(s), "v"(b));
+    return r;
+}
+
 // a.lo^2 + a.hi^2 of two int16 halves (VOP3P dot with a zero accumulator)
 __device__ __forceinline__ int dot2_sq(u32 a)
 {
@@ -467,10 +520,10 @@ __device__ __forceinline__ Win<PPL> load_row_bytes(const GMEM uint8_t *rowp, int
 
 // Stores of one output row for one lane, from Gx, Gy, Hp = Gd+/2 and
 // Hm = Gd-/2 (two-directional operators: Gx and Gy only; Hp, Hm unread).
-template <int NP, bool DIR, bool FAST, int OPR>
+template <int NP, bool DIR, bool FAST, int OPR, bool LUT>
 __device__ __forceinline__ void store_row(const U8Job &J, int yo, int xo, bool row_ok,
                                           const v2s (&Gx)[NP], const v2s (&Hp)[NP],
-                                          const v2s (&Gy)[NP], const v2s (&Hm)[NP])
+                                          const v2s (&Gy)[NP], const v2s (&Hm)[NP], lds_u8 *lut)
 {
     constexpr int PPL = 2 * NP;
     if (!FAST && !row_ok) return;
@@ -479,6 +532,7 @@ __device__ __forceinline__ void store_row(const U8Job &J, int yo, int xo, bool r
     const bool full = FAST || nvalid >= PPL;
     if (DIR ? J.mag != nullptr : true) {
         u32 out[PPL / 4];
+        u32 mb[LUT ? PPL : 1];   // LUT: the rounded byte of every pixel
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
             // S = Gx^2 + Gy^2 + Gd^2 + Gdt^2 = Gx^2 + Gy^2 + 2 (Hp^2 + Hm^2):
@@ -497,11 +551,22 @@ __device__ __forceinline__ void store_row(const U8Job &J, int yo, int xo, bool r
                 sh = dot2_sq(xyh);
             }
             const int ql = j, qh = j + NP;   // pixel indices inside the lane
-            const float fl = mag_f(sl), fh = mag_f(sh);
-            // the first byte written into a word starts from any value: all
-            // four bytes of every word are overwritten
-            out[ql >> 2] = __builtin_amdgcn_cvt_pk_u8_f32(fl, ql & 3, (ql & 3) ? out[ql >> 2] : __builtin_bit_cast(u32, fl));
-            out[qh >> 2] = __builtin_amdgcn_cvt_pk_u8_f32(fh, qh & 3, (qh & 3) ? out[qh >> 2] : __builtin_bit_cast(u32, fh));
+            if constexpr (LUT) {
+                mb[ql] = lut_mag(lut, sl);
+                mb[qh] = lut_mag(lut, sh);
+            } else {
+                const float fl = mag_f(sl), fh = mag_f(sh);
+                // the first byte written into a word starts from any value: all
+                // four bytes of every word are overwritten
+                out[ql >> 2] = __builtin_amdgcn_cvt_pk_u8_f32(fl, ql & 3, (ql & 3) ? out[ql >> 2] : __builtin_bit_cast(u32, fl));
+                out[qh >> 2] = __builtin_amdgcn_cvt_pk_u8_f32(fh, qh & 3, (qh & 3) ? out[qh >> 2] : __builtin_bit_cast(u32, fh));
+            }
+        }
+        if constexpr (LUT) {
+            // three shift-ors a word (each byte is zero-extended)
+#pragma unroll
+            for (int w = 0; w < PPL / 4; ++w)
+                out[w] = lshl_or(lshl_or(mb[4 * w + 3], 8, mb[4 * w + 2]), 16, lshl_or(mb[4 * w + 1], 8, mb[4 * w]));
         }
         GMEM uint8_t *p = ((GMEM uint8_t *)J.mag + (int64_t)yo * J.mag_pitch) + (unsigned)xo;
         if (FAST || full) {
@@ -592,8 +657,8 @@ struct Sweep {
 // ranges); otherwise one loop that leaves after any step (short row ranges
 // of the batched kernel, where the tail's extra code costs more than the
 // waits it saves).
-template <int PPL, int OFF, bool ALIGNED, bool DIR, bool FAST, bool EDGE, int OPR, int BM, bool BLOCKS = true>
-__device__ __forceinline__ void sweep(const U8Job &J, const Sweep &g)
+template <int PPL, int OFF, bool ALIGNED, bool DIR, bool FAST, bool EDGE, int OPR, int BM, bool LUT, bool BLOCKS = true>
+__device__ __forceinline__ void sweep(const U8Job &J, const Sweep &g, lds_u8 *lut)
 {
     static_assert(!EDGE || FAST, "edge fix-ups by mask exist for fast waves only");
     constexpr int NP = PPL / 2;
@@ -707,7 +772,7 @@ __device__ __forceinline__ void sweep(const U8Job &J, const Sweep &g)
             responses_y<NP>(vr, A2r[s2], Gy, Hp);
             responses_x<NP>(HR[s0], HR[s1], HR[s2], HR[s3], HR[s4], HS[s0], HS[s2], HS[s4], Gx, Hm);
         }
-        store_row<NP, DIR, FAST, OPR>(J, yo0 + i, xo, FAST || i < nrow, Gx, Hp, Gy, Hm);
+        store_row<NP, DIR, FAST, OPR, LUT>(J, yo0 + i, xo, FAST || i < nrow, Gx, Hp, Gy, Hm, lut);
         // keep each row's work in its own scheduling region: interleaving
         // rows buys little ILP and costs the registers of a second row
         __builtin_amdgcn_sched_barrier(0);
@@ -759,6 +824,11 @@ __device__ __forceinline__ void sweep(const U8Job &J, const Sweep &g)
 
 constexpr int kWaves = 4;   // waves per workgroup
 
+// Kernels that run two waves per SIMD (8 per CU, two 4-wave workgroups) round
+// through the table in LDS: two 64 KiB copies fit in a CU's 160 KiB.  The
+// others (three waves per SIMD) keep the square-root rounding.
+constexpr bool use_lut(int waves_per_simd) { return waves_per_simd == 2; }
+
 // Waves per SIMD the single-image kernel is compiled for (register budget
 // 512 / waves): 16 pixels per lane needs ~220 VGPRs (2 waves), 8 pixels per
 // lane ~134 (3 waves), or 128 with a few spilled values (4 waves).  The
@@ -793,6 +863,13 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
     single_waves(PPL, OPR, ALIGNED, DIR), single_waves(PPL, OPR, ALIGNED, DIR)))) void k_u8_single(U8Job J, int nchunk)
 {
     constexpr int TW = 16 * PPL;
+    constexpr bool LUT = use_lut(single_waves(PPL, OPR, ALIGNED, DIR));
+    __shared__ __attribute__((aligned(16))) uint8_t lut[LUT ? kLutSize : 16];
+    if constexpr (LUT) {
+        lut_fill<64 * kWaves>(lut);
+        __syncthreads();   // before any wave leaves
+    }
+    lds_u8 *lutp = (lds_u8 *)lut;
     const int w = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ntxw = (J.ntx + 3) >> 2;
     if (w >= ntxw * nchunk) return;
@@ -814,11 +891,11 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
     // fix-ups of their group halos
     const bool fast = ALIGNED && (strip * 4 + 4) * TW <= J.Wo;
     if (fast && !g.fix_right && !g.fix_left)
-        sweep<PPL, OFF, ALIGNED, DIR, true, false, OPR, BM>(J, g);
+        sweep<PPL, OFF, ALIGNED, DIR, true, false, OPR, BM, LUT>(J, g, lutp);
     else if (fast)
-        sweep<PPL, OFF, ALIGNED, DIR, true, true, OPR, BM>(J, g);
+        sweep<PPL, OFF, ALIGNED, DIR, true, true, OPR, BM, LUT>(J, g, lutp);
     else
-        sweep<PPL, OFF, ALIGNED, DIR, false, false, OPR, BM>(J, g);
+        sweep<PPL, OFF, ALIGNED, DIR, false, false, OPR, BM, LUT>(J, g, lutp);
 }
 
 

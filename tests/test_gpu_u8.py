@@ -176,12 +176,14 @@ def test_transpose_property_full_size(sobel_lib, gpu):
     assert torch.equal(m1.t().contiguous(), m2)
 
 
-def test_rounding_exhaustive(oracle_mod, sobel_lib, gpu):
-    """The library's uint8 rounding for every S in [0, 70000] and large S up
-    to the maximum the operator reaches (599,270,400) and beyond."""
-    S = np.concatenate([np.arange(0, 70001), np.array([64770, 64771, 65280, 10**6, 299635200, 599270400,
-                                                       2**31 - 1])])
-    got = sobel_lib.debug_round_mag(torch.from_numpy(S.astype(np.int32)).to(gpu)).cpu().numpy()
+@pytest.mark.parametrize("method", [0, 1])
+def test_rounding_exhaustive(oracle_mod, sobel_lib, gpu, method):
+    """Both of the library's uint8 roundings (fp32 square root; LDS table) for
+    every S in [0, 70000] and large S up to the maximum the operator reaches
+    (599,270,400) and beyond."""
+    S = np.concatenate([np.arange(0, 70001), np.array([64770, 64771, 65280, 65281, 65535, 65536, 10**6,
+                                                       299635200, 599270400, 2**31 - 1])])
+    got = sobel_lib.debug_round_mag(torch.from_numpy(S.astype(np.int32)).to(gpu), method).cpu().numpy()
     want = np.array([min(255, oracle_mod.round_sqrt(int(s))) for s in S], dtype=np.uint8)
     assert np.array_equal(got, want)
 
