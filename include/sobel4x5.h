@@ -328,15 +328,27 @@ int sobel4x5_validate_f32(const float *src, int32_t batch, int32_t width, int32_
 int sobel4x5_debug_round_mag(const int32_t *S, uint8_t *out, int64_t n, void *stream);
 
 /*
- * The same with a choice of the library's two implementations of that
- * rounding: method 0 converts S to fp32 and rounds its square root (the
- * kernels that run three waves per SIMD); method 1 reads a table of the
- * rounded value of every S below 2^16, held in LDS, at min(S, 65535) (the
- * kernels that run two waves per SIMD, the 8192^2 magnitude kernel among
- * them).  Both must give the same byte for every S.  EINVAL for another
- * method.
+ * The same with a choice of the two implementations of that rounding in
+ * the two-directional operators' kernels: method 0 converts S to fp32 and
+ * rounds its square root (kernels that run three waves per SIMD); method 1
+ * reads a table of the rounded value of every S below 2^16, held in LDS, at
+ * min(S, 65535) (kernels that run two waves per SIMD).  Both must give the
+ * same byte for every S.  EINVAL for another method.
  */
 int sobel4x5_debug_round_mag_ex(const int32_t *S, uint8_t *out, int64_t n, int32_t method, void *stream);
+
+/*
+ * Diagnostic: the rounding of the four-directional kernels, step for step.
+ * They never form S; they form E1 = (Gx + Gy)/2, E2 = (Gx - Gy)/2,
+ * Hp = (Gd + Gdt)/2 and Hm = (Gd - Gdt)/2 (all int16), for which
+ * S = 2 (E1^2 + E2^2 + Hp^2 + Hm^2) (Eq. (sobel5_2)), sum the four squares
+ * on int16 lanes saturating at 32767, and read min(255, round(sqrt(2 T)))
+ * from a table in LDS.  q: n quadruples (E1, E2, Hp, Hm) of int16 (device,
+ * 8 bytes each); out[i] (device) receives the byte of quadruple i, which
+ * must equal min(255, round(sqrt(S))) for every int16 quadruple.
+ * EINVAL for n < 0 or NULL pointers with n > 0.
+ */
+int sobel4x5_debug_round_quad(const int16_t *q, uint8_t *out, int64_t n, void *stream);
 
 /*
  * Diagnostic: plain device-to-device copy of nbytes (a multiple of 16;

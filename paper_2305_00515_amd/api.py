@@ -85,6 +85,7 @@ def _load() -> ctypes.CDLL:
         "sobel4x5_pipe_destroy": [P],
         "sobel4x5_debug_round_mag": [P, P, I64, P],
         "sobel4x5_debug_round_mag_ex": [P, P, I64, I32, P],
+        "sobel4x5_debug_round_quad": [P, P, I64, P],
         "sobel4x5_debug_copy": [P, P, I64, P],
         "sobel4x5_debug_inject_failure": [I32],
         "sobel4x5_status_string": [ctypes.c_int],
@@ -461,6 +462,21 @@ def debug_round_mag(S: torch.Tensor, method: int = 0) -> torch.Tensor:
     out = torch.empty(S.shape, dtype=torch.uint8, device=S.device)
     _check(lib.sobel4x5_debug_round_mag_ex(S.data_ptr(), out.data_ptr(), S.numel(), int(method), _stream(S)),
            "sobel4x5_debug_round_mag_ex")
+    return out
+
+
+def debug_round_quad(q: torch.Tensor) -> torch.Tensor:
+    """The four-directional kernels' rounding of int16 quadruples
+    (E1, E2, Hp, Hm), shape [n, 4]: min(255, round(sqrt(S))) with
+    S = 2 (E1^2 + E2^2 + Hp^2 + Hm^2), through the saturated int16 sum and
+    the LDS table."""
+    _need_cuda(q, torch.int16, "q")
+    if q.dim() != 2 or q.shape[1] != 4:
+        raise ValueError("q must have shape [n, 4]")
+    q = q.contiguous()
+    out = torch.empty(q.shape[0], dtype=torch.uint8, device=q.device)
+    _check(lib.sobel4x5_debug_round_quad(q.data_ptr(), out.data_ptr(), q.shape[0], _stream(q)),
+           "sobel4x5_debug_round_quad")
     return out
 
 

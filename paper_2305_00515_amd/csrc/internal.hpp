@@ -108,6 +108,8 @@ hipError_t launch_fingerprint(const void *base, int64_t pitch, int64_t row_bytes
                               hipStream_t stream);
 // method 0: the square-root rounding; 1: the LDS table (u8_sweep.hpp)
 hipError_t launch_round_mag(const int32_t *S, uint8_t *out, int64_t n, int method, hipStream_t stream);
+// The four-directional sweep's rounding of n int16 quadruples (E1, E2, Hp, Hm)
+hipError_t launch_round_quad(const int16_t *q, uint8_t *out, int64_t n, hipStream_t stream);
 
 // fp32 path (pointers and strides as in the public header).
 struct F32Args {

@@ -203,17 +203,19 @@ int device_cus()
     return n;
 }
 
-U8Shape default_shape(int32_t Wo, int32_t Ho, int32_t dir_type)
+U8Shape default_shape(int32_t Wo, int32_t Ho, int32_t dir_type, int32_t op = SOBEL4X5_OP_4DIR_5X5)
 {
     U8Shape s;
-    // 16 pixels per lane (1024-column strips) only where that shape alone
-    // fills one round of resident waves (2 per SIMD, 8 per CU) with its
-    // 2-row minimum ranges.  Smaller images have too few waves, and 8 pixels
-    // per lane doubles them and halves each one's serial work (1024^2:
-    // 4.55 against 5.42 us per launch, 1920x1080: 6.5 against 7.3 us).
+    // The four-directional magnitude kernel (binomial form) runs 8 pixels
+    // per lane at three waves per SIMD at every size: at 16 it needs more
+    // than the 256 registers of two waves per SIMD (8192^2: 46.2 against
+    // 60.4 us; 16384^2: 162 against 180 us).  The two-directional operators
+    // take 16 pixels per lane (1024-column strips) only where that shape
+    // alone fills one round of resident waves (2 per SIMD, 8 per CU) with
+    // its 2-row minimum ranges; smaller images have too few waves.
     const int64_t strips16 = (Wo + 1023) / 1024;
     const bool fills = strips16 * (Ho / 2) >= 8 * (int64_t)device_cus();
-    s.ppl = (fills && dir_type == SOBEL4X5_DIR_NONE) ? 16 : 8;
+    s.ppl = (fills && dir_type == SOBEL4X5_DIR_NONE && op != SOBEL4X5_OP_4DIR_5X5) ? 16 : 8;
     const int ppl = env_int("SOBEL4X5_U8_PPL", 0);
     if (ppl == 8 || ppl == 16) s.ppl = ppl;
     s.th = 32;
@@ -860,7 +862,7 @@ int sobel4x5_u8_op(const uint8_t *src, int32_t width, int32_t height, int64_t sr
     }
     U8Job j = make_job(src, width, height, src_pitch, Wo, Ho, out->mag, out->mag_pitch,
                        out->dir_type ? dirs : nullptr, out->dir_pitch, out->dir_type);
-    U8Shape s = default_shape(Wo, Ho, out->dir_type);
+    U8Shape s = default_shape(Wo, Ho, out->dir_type, op);
     u8_tile(j, s);
     // The two-directional operators are lighter on arithmetic, so the 4-row
     // prologue each wave re-reads weighs more: on large images they take
@@ -1179,6 +1181,14 @@ int sobel4x5_debug_round_mag_ex(const int32_t *S, uint8_t *out, int64_t n, int32
 int sobel4x5_debug_round_mag(const int32_t *S, uint8_t *out, int64_t n, void *stream)
 {
     return sobel4x5_debug_round_mag_ex(S, out, n, 0, stream);
+}
+
+int sobel4x5_debug_round_quad(const int16_t *q, uint8_t *out, int64_t n, void *stream)
+{
+    if (n < 0 || (n > 0 && (!q || !out))) return fail(SOBEL4X5_EINVAL, "bad arguments");
+    if (n > (INT64_MAX / 8)) return fail(SOBEL4X5_EINVAL, "n too large");
+    hipError_t e = launch_round_quad(q, out, n, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_debug_round_quad launch");
 }
 
 int sobel4x5_pipe_create(int32_t max_width, int32_t max_height, int32_t depth, sobel4x5_pipe *out)

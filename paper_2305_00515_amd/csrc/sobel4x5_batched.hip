@@ -57,12 +57,10 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
                                                             uint32_t *queue, int TH)
 {
     constexpr int TW = 16 * PPL;
-    constexpr bool LUT = use_lut(single_waves(PPL, kOp4x5, ALIGNED, DIR));
-    __shared__ __attribute__((aligned(16))) uint8_t lut[LUT ? kLutSize : 16];
-    if constexpr (LUT) {
-        lut_fill<64 * kWaves>(lut);
-        __syncthreads();
-    }
+    constexpr int WV = single_waves(PPL, kOp4x5, ALIGNED, DIR);
+    constexpr bool LUT = use_lut(WV);
+    __shared__ __attribute__((aligned(16))) uint8_t lut[lut_bytes(kOp4x5, DIR, WV)];
+    lut_setup<kOp4x5, DIR, WV, 64 * kWaves>(lut);
     lds_u8 *lutp = (lds_u8 *)lut;
     const int lane = threadIdx.x & 63;
     // one tile of the table: returns false when it has no rows

@@ -74,6 +74,32 @@ __global__ __launch_bounds__(256) void k_round_mag_lut(const int32_t *S, uint8_t
     if (i < n) out[i] = (uint8_t)lut_mag((lds_u8 *)lut, S[i]);
 }
 
+// The four-directional sweep's rounding, step for step: quadruples
+// (E1, E2, Hp, Hm) of int16 in pairs on the packed halves of a register,
+// T = E1^2 + E2^2 + Hp^2 + Hm^2 saturated at 2^15 - 1 by the clamped
+// multiply-adds, then the table of round(sqrt(2 T)) in LDS.
+__global__ __launch_bounds__(256) void k_round_quad(const int16_t *q, uint8_t *out, int64_t n)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t lut[kLutTSize];
+    lut_fill_t<256>(lut);
+    __syncthreads();
+    const int64_t i = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    u32 c[4];
+    for (int k = 0; k < 4; ++k) {
+        const u32 lo = (uint16_t)q[4 * i + k];
+        const u32 hi = i + 1 < n ? (uint16_t)q[4 * (i + 1) + k] : 0u;
+        c[k] = lo | (hi << 16);
+    }
+    u32 T = sq_sat(c[0]);
+    T = sq_sat_acc(c[1], T);
+    T = sq_sat_acc(c[2], T);
+    T = sq_sat_acc(c[3], T);
+    const lds_u8 *lp = (lds_u8 *)lut;
+    out[i] = (uint8_t)lp[T & 0xffffu];
+    if (i + 1 < n) out[i + 1] = (uint8_t)lp[T >> 16];
+}
+
 }  // namespace
 
 bool u8_rows_aligned(const U8Job &j)
@@ -117,6 +143,15 @@ hipError_t launch_fingerprint(const void *base, int64_t pitch, int64_t row_bytes
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_fingerprint, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<const uint8_t *>(base),
                        pitch, row_bytes, rows, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_round_quad(const int16_t *q, uint8_t *out, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 511) / 512;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_round_quad, dim3((unsigned)blocks), dim3(256), 0, st, q, out, n);
     return hipGetLastError();
 }
 

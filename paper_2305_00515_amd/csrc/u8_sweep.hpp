@@ -92,6 +92,10 @@ constexpr int kOp4x5 = 0;   // Eq. (sobel5_1) + Eq. (sobel5_2): four directions,
 constexpr int kOp2x5 = 1;   // the 0 and 90 deg filters of Eq. (sobel5_1) alone
 constexpr int kOp2x3 = 2;   // Eq. (sobel3_1) + Eq. (sobel3_2): the 3x3 pair
 
+// Kernels in the binomial form (sweep4): the four-directional operator
+// without directional planes (see sweep).
+constexpr bool binomial_form(int opr, bool dir) { return opr == kOp4x5 && !dir; }
+
 // v_perm selector: byte0 <- byte `lob` of the low source, byte2 <- byte
 // `hib` of the high source, bytes 1 and 3 <- 0: two zero-extended pixels.
 constexpr u32 pair_sel(int lob, int hib)
@@ -155,6 +159,56 @@ __device__ __forceinline__ void lut_fill(uint8_t *lut)
 }
 
 __device__ __forceinline__ u32 lut_mag(lds_u8 *lut, int S) { return lut[min((u32)S, (u32)kLutSize - 1u)]; }
+
+// The four-directional sweep forms T = S / 2 (below) saturated to 2^15 - 1
+// and rounds through a table of min(255, round(sqrt(2 T))) for T < 2^15:
+// k for 2T in (k^2 - k, k^2 + k], 255 from 2T >= 255^2 + 256 (T >= 32386),
+// so the saturated value rounds like the exact one.
+constexpr int kLutTSize = 1 << 15;
+struct MagLutT {
+    uint8_t v[kLutTSize];
+};
+constexpr MagLutT make_mag_lut_t()
+{
+    MagLutT t{};
+    int T = 1;
+    for (int k = 1; k <= 255; ++k)
+        for (const int hi = k * k + k; 2 * T <= hi && T < kLutTSize; ++T) t.v[T] = (uint8_t)k;
+    for (; T < kLutTSize; ++T) t.v[T] = 255;
+    return t;
+}
+constexpr MagLutT kMagLutT = make_mag_lut_t();
+static_assert(kMagLutT.v[0] == 0 && kMagLutT.v[1] == 1 && kMagLutT.v[2] == 2 && kMagLutT.v[544] == 33 &&
+                  kMagLutT.v[32385] == 254 && kMagLutT.v[32386] == 255 && kMagLutT.v[kLutTSize - 1] == 255,
+              "rounding table of T = S/2");
+
+template <int THREADS>
+__device__ __forceinline__ void lut_fill_t(uint8_t *lut)
+{
+    static_assert(kLutTSize % (16 * THREADS) == 0, "table split");
+    constexpr int kPer = kLutTSize / (16 * THREADS);
+    uint4 v[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) v[k] = reinterpret_cast<const uint4 *>(kMagLutT.v)[threadIdx.x + k * THREADS];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) reinterpret_cast<uint4 *>(lut)[threadIdx.x + k * THREADS] = v[k];
+}
+
+// Per 16-bit half: min(32767, a^2 + acc) for acc >= 0.  The clamp bit of
+// v_pk_mad_i16 saturates the exact a * b + c of each half to the int16
+// range, so a sum of squares that overflows int16 reads 32767.
+__device__ __forceinline__ u32 sq_sat(u32 a)
+{
+    u32 r;
+    asm("v_pk_mad_i16 %0, %1, %1, 0 clamp" : "=v"(r) : "v"(a));
+    return r;
+}
+__device__ __forceinline__ u32 sq_sat_acc(u32 a, u32 acc)
+{
+    u32 r;
+    asm("v_pk_mad_i16 %0, %1, %1, %2 clamp" : "=v"(r) : "v"(a), "v"(acc));
+    return r;
+}
 
 // (a << s) | b in one v_lshl_or_b32
 __device__ __forceinline__ u32 lshl_or(u32 a, int s, u32 b)
@@ -293,6 +347,38 @@ __device__ __forceinline__ void responses_3x3(const v2s (&hs0)[NP], const v2s (&
     for (int j = 0; j < NP; ++j) {
         Gx[j] = hs1[j] * k2 + (hs0[j] + hs2[j]);
         Gy[j] = a2[j + 2] * k2 + (a2[j + 1] + a2[j + 3]);
+    }
+}
+
+// Row filters of one input row for the four-directional operator in the
+// binomial form (see sweep4).  R[k] holds the pixels at column k - 2 (relative
+// to the lane's first centre), k in [0, NP + 4).  With the running sums
+// b1 = (1 + v) p, b2 = (1 + v)^2 p, b3 = (1 + v)^3 p (anchored at their
+// first tap), every filter of the row is a few adds of them:
+//   b3[c]               [1, 3, 3, 1] at columns c .. c+3, for the smoothed
+//                       image P (columns -2 .. NP-2);
+//   hs = p[+1] - p[-1]  = b1[x] - b1[x-1];
+//   hr = [-1,-2,0,2,1]  = b3[x-1] - b3[x-2];
+//   ch = [3,3,1,3,3]    = 3 (b1[x-2] + b1[x+1]) + p[x];
+//   mh = [1,6,8,6,1]    = (b3[x-2] + b3[x-1]) + 2 (b1[x-1] + p[x+1]).
+template <int NP>
+__device__ __forceinline__ void row_filters_bin(const v2s (&R)[NP + 4], v2s (&b3)[NP + 1], v2s (&hs)[NP],
+                                                v2s (&hr)[NP], v2s (&ch)[NP], v2s (&mh)[NP])
+{
+    const v2s k2 = kconst<2>(), k3 = kconst<3>();
+    v2s b1[NP + 3], b2[NP + 2];
+#pragma unroll
+    for (int k = 0; k < NP + 3; ++k) b1[k] = R[k] + R[k + 1];
+#pragma unroll
+    for (int k = 0; k < NP + 2; ++k) b2[k] = b1[k] + b1[k + 1];
+#pragma unroll
+    for (int k = 0; k < NP + 1; ++k) b3[k] = b2[k] + b2[k + 1];
+#pragma unroll
+    for (int x = 0; x < NP; ++x) {
+        hs[x] = b1[x + 2] - b1[x + 1];
+        hr[x] = b3[x + 1] - b3[x];
+        ch[x] = (b1[x] + b1[x + 3]) * k3 + R[x + 2];
+        mh[x] = (b1[x + 1] + R[x + 3]) * k2 + (b3[x] + b3[x + 1]);
     }
 }
 
@@ -518,6 +604,75 @@ __device__ __forceinline__ Win<PPL> load_row_bytes(const GMEM uint8_t *rowp, int
     return w;
 }
 
+// Directional planes of one output row for one lane (int16 or int32, as the
+// job asks), from Gx, Gy, Hp = Gd+/2 and Hm = Gd-/2 (two-directional
+// operators: Gx and Gy only).
+template <int NP, bool FAST, int OPR>
+__device__ __forceinline__ void store_dir(const U8Job &J, int yo, int xo, bool row_ok, const v2s (&Gx)[NP],
+                                          const v2s (&Hp)[NP], const v2s (&Gy)[NP], const v2s (&Hm)[NP])
+{
+    constexpr int PPL = 2 * NP;
+    if (!FAST && !row_ok) return;
+    const int nvalid = J.Wo - xo;          // pixels of this lane inside the image
+    if (!FAST && nvalid <= 0) return;
+    const bool full = FAST || nvalid >= PPL;
+    if (J.dir_type != 0) {
+        // plane order: 0 deg Gx, 45 deg Gd, 90 deg Gy, 135 deg Gdt (the
+        // two-directional operators write planes 0 and 2)
+        v2s P[4][NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            P[0][j] = Gx[j];
+            P[2][j] = Gy[j];
+            if constexpr (OPR == kOp4x5) {
+                P[1][j] = Hp[j] + Hm[j];          // Gd  = (Gd+ + Gd-)/2 = Hp + Hm
+                P[3][j] = Hp[j] - Hm[j];          // Gdt = (Gd+ - Gd-)/2 = Hp - Hm
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (OPR != kOp4x5 && (k & 1)) continue;
+            GMEM char *base = (GMEM char *)J.dir[k] + (int64_t)yo * J.dir_pitch;
+            if (J.dir_type == 1) {
+                u32 o[NP];   // int16 pixels (2m, 2m+1)
+#pragma unroll
+                for (int m = 0; m < NP; ++m) {
+                    const int a = 2 * m;
+                    o[m] = a < NP ? perm(U2(P[k][a + 1]), U2(P[k][a]), 0x05040100u)
+                                  : perm(U2(P[k][a - NP + 1]), U2(P[k][a - NP]), 0x07060302u);
+                }
+                GMEM int16_t *p = reinterpret_cast<GMEM int16_t *>(base) + xo;
+                if (FAST || full) {
+#pragma unroll
+                    for (int m = 0; m < NP; m += 4)
+                        *reinterpret_cast<GMEM gv4u_u *>(p + 2 * m) = gv4u{o[m], o[m + 1], o[m + 2], o[m + 3]};
+                } else {
+#pragma unroll
+                    for (int q = 0; q < PPL; ++q)
+                        if (q < nvalid) p[q] = (int16_t)(o[q >> 1] >> (16 * (q & 1)));
+                }
+            } else {
+                int o[PPL];
+#pragma unroll
+                for (int j = 0; j < NP; ++j) {
+                    o[j] = P[k][j].x;
+                    o[j + NP] = P[k][j].y;
+                }
+                GMEM int32_t *p = reinterpret_cast<GMEM int32_t *>(base) + xo;
+                if (FAST || full) {
+#pragma unroll
+                    for (int q = 0; q < PPL; q += 4)
+                        *reinterpret_cast<GMEM gv4u_u *>(p + q) = gv4u{(u32)o[q], (u32)o[q + 1], (u32)o[q + 2], (u32)o[q + 3]};
+                } else {
+#pragma unroll
+                    for (int q = 0; q < PPL; ++q)
+                        if (q < nvalid) p[q] = o[q];
+                }
+            }
+        }
+    }
+}
+
 // Stores of one output row for one lane, from Gx, Gy, Hp = Gd+/2 and
 // Hm = Gd-/2 (two-directional operators: Gx and Gy only; Hp, Hm unread).
 template <int NP, bool DIR, bool FAST, int OPR, bool LUT>
@@ -580,61 +735,7 @@ __device__ __forceinline__ void store_row(const U8Job &J, int yo, int xo, bool r
                 if (q < nvalid) p[q] = (uint8_t)(out[q >> 2] >> (8 * (q & 3)));
         }
     }
-    if (DIR && J.dir_type != 0) {
-        // plane order: 0 deg Gx, 45 deg Gd, 90 deg Gy, 135 deg Gdt (the
-        // two-directional operators write planes 0 and 2)
-        v2s P[4][NP];
-#pragma unroll
-        for (int j = 0; j < NP; ++j) {
-            P[0][j] = Gx[j];
-            P[2][j] = Gy[j];
-            if constexpr (OPR == kOp4x5) {
-                P[1][j] = Hp[j] + Hm[j];          // Gd  = (Gd+ + Gd-)/2 = Hp + Hm
-                P[3][j] = Hp[j] - Hm[j];          // Gdt = (Gd+ - Gd-)/2 = Hp - Hm
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (OPR != kOp4x5 && (k & 1)) continue;
-            GMEM char *base = (GMEM char *)J.dir[k] + (int64_t)yo * J.dir_pitch;
-            if (J.dir_type == 1) {
-                u32 o[NP];   // int16 pixels (2m, 2m+1)
-#pragma unroll
-                for (int m = 0; m < NP; ++m) {
-                    const int a = 2 * m;
-                    o[m] = a < NP ? perm(U2(P[k][a + 1]), U2(P[k][a]), 0x05040100u)
-                                  : perm(U2(P[k][a - NP + 1]), U2(P[k][a - NP]), 0x07060302u);
-                }
-                GMEM int16_t *p = reinterpret_cast<GMEM int16_t *>(base) + xo;
-                if (FAST || full) {
-#pragma unroll
-                    for (int m = 0; m < NP; m += 4)
-                        *reinterpret_cast<GMEM gv4u_u *>(p + 2 * m) = gv4u{o[m], o[m + 1], o[m + 2], o[m + 3]};
-                } else {
-#pragma unroll
-                    for (int q = 0; q < PPL; ++q)
-                        if (q < nvalid) p[q] = (int16_t)(o[q >> 1] >> (16 * (q & 1)));
-                }
-            } else {
-                int o[PPL];
-#pragma unroll
-                for (int j = 0; j < NP; ++j) {
-                    o[j] = P[k][j].x;
-                    o[j + NP] = P[k][j].y;
-                }
-                GMEM int32_t *p = reinterpret_cast<GMEM int32_t *>(base) + xo;
-                if (FAST || full) {
-#pragma unroll
-                    for (int q = 0; q < PPL; q += 4)
-                        *reinterpret_cast<GMEM gv4u_u *>(p + q) = gv4u{(u32)o[q], (u32)o[q + 1], (u32)o[q + 2], (u32)o[q + 3]};
-                } else {
-#pragma unroll
-                    for (int q = 0; q < PPL; ++q)
-                        if (q < nvalid) p[q] = o[q];
-                }
-            }
-        }
-    }
+    if (DIR) store_dir<NP, FAST, OPR>(J, yo, xo, row_ok, Gx, Hp, Gy, Hm);
 }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -657,8 +758,8 @@ struct Sweep {
 // ranges); otherwise one loop that leaves after any step (short row ranges
 // of the batched kernel, where the tail's extra code costs more than the
 // waits it saves).
-template <int PPL, int OFF, bool ALIGNED, bool DIR, bool FAST, bool EDGE, int OPR, int BM, bool LUT, bool BLOCKS = true>
-__device__ __forceinline__ void sweep(const U8Job &J, const Sweep &g, lds_u8 *lut)
+template <int PPL, int OFF, bool ALIGNED, bool DIR, bool FAST, bool EDGE, int OPR, int BM, bool LUT, bool BLOCKS>
+__device__ __forceinline__ void sweep_sep(const U8Job &J, const Sweep &g, lds_u8 *lut)
 {
     static_assert(!EDGE || FAST, "edge fix-ups by mask exist for fast waves only");
     constexpr int NP = PPL / 2;
@@ -822,12 +923,293 @@ __device__ __forceinline__ void sweep(const U8Job &J, const Sweep &g, lds_u8 *lu
     }
 }
 
+// Magnitude bytes of one output row for one lane (mb[q]: pixel q of the
+// lane, zero-extended), packed with three shift-ors a word.
+template <int PPL, bool FAST>
+__device__ __forceinline__ void store_mag_bytes(const U8Job &J, int yo, int xo, bool row_ok, const u32 (&mb)[PPL])
+{
+    if (!FAST && !row_ok) return;
+    const int nvalid = J.Wo - xo;
+    if (!FAST && nvalid <= 0) return;
+    u32 out[PPL / 4];
+#pragma unroll
+    for (int w = 0; w < PPL / 4; ++w)
+        out[w] = lshl_or(lshl_or(mb[4 * w + 3], 8, mb[4 * w + 2]), 16, lshl_or(mb[4 * w + 1], 8, mb[4 * w]));
+    GMEM uint8_t *p = ((GMEM uint8_t *)J.mag + (int64_t)yo * J.mag_pitch) + (unsigned)xo;
+    if (FAST || nvalid >= PPL) {
+        if constexpr (PPL == 16)
+            *reinterpret_cast<GMEM gv4u_u *>(p) = gv4u{out[0], out[1], out[2], out[3]};
+        else
+            *reinterpret_cast<GMEM gv2u_u *>(p) = gv2u{out[0], out[1]};
+    } else {
+#pragma unroll
+        for (int q = 0; q < PPL; ++q)
+            if (q < nvalid) p[q] = (uint8_t)(out[q >> 2] >> (8 * (q & 3)));
+    }
+}
+
+// Four-directional 5x5 sweep in the binomial form, magnitude only.  With u
+// one row down and v one column right, the 0 and 90 deg filters of
+// Eq. (sobel5_1) share the factor (1 + u)^3 (1 + v)^3:
+//   K_x + K_y = 2 (1 + u)^3 (1 + v)^3 (uv - 1),
+//   K_x - K_y = 2 (1 + u)^3 (1 + v)^3 (v - u),
+// so with P the [1,3,3,1] x [1,3,3,1] smoothing of the image, anchored at
+// its top-left tap,
+//   E1 = (Gx + Gy) / 2 = P(y-1, x-1) - P(y-2, x-2),
+//   E2 = (Gx - Gy) / 2 = P(y-2, x-1) - P(y-1, x-2),
+// and Gx = E1 + E2, Gy = E1 - E2.  The diagonal pair is Hp = Gd+/2 and
+// Hm = Gd-/2 (K_d+- = K_d +- K_dt, Eq. (sobel5_kd+-); Gd = Hp + Hm and
+// Gdt = Hp - Hm, Eq. (sobel5_kd)), both from row filters:
+//   Hp = ch(y+2) - ch(y-2) + mh(y+1) - mh(y-1)       (the rows of K_d+ / 2)
+//   Hm = [3,3,1,3,3]_v hr + [-5,0,6,0,-5]_v hs       (Eq. (sobel5_4) / 2)
+// Then S = Gx^2 + Gy^2 + Gd^2 + Gdt^2 = 2 (E1^2 + E2^2 + Hp^2 + Hm^2) = 2 T.
+// |E| <= 16320 and |H| <= 8925, so T is summed on the packed int16 halves,
+// saturating at 2^15 - 1, and rounded through the table of round(sqrt(2 T)):
+// four multiply-adds and one LDS byte read a pixel pair.
+//
+// Vertical passes on a ring of five input rows (ring slot = input slot mod
+// 5, a compile-time index in the unrolled loop): the P smoothing as three
+// running pair sums, Hp and Hm as partial sums of the outputs still open
+// that each new row adds its terms to (Hp kept negated until its last row).
+// The LDS reads of one row's magnitudes are issued at the end of its step
+// and consumed by the next step's store, so their latency hides behind a
+// whole row of arithmetic.
+template <int PPL, int OFF, bool ALIGNED, bool FAST, bool EDGE, int BM, bool BLOCKS>
+__device__ __forceinline__ void sweep4(const U8Job &J, const Sweep &g, lds_u8 *lut)
+{
+    static_assert(!EDGE || FAST, "edge fix-ups by mask exist for fast waves only");
+    constexpr int NP = PPL / 2;
+    const int lane16 = threadIdx.x & 15;
+    const int xo = g.xo, yo0 = g.yo0, nrow = g.nrow, niter = g.niter;
+    const int W = J.W;
+    const int ymax = J.H - 1;
+    const int yin0 = yo0 + OFF - 2;                  // input row of window slot 0
+    const int tlast = niter + 3;                     // last input row slot needed
+
+    const LoadCols lc = load_columns(xo, lane16, W, PPL);
+    const unsigned ldx = lc.ldx, hx = lc.hx;
+    const bool fix_right = FAST ? false : g.fix_right;
+    const bool fix_left = FAST ? false : g.fix_left;
+    const EdgeFix efix = edge_fix<PPL, OFF, BM>(lane16, xo, W, EDGE && g.fix_left, EDGE && g.fix_right);
+
+    const GMEM uint8_t *src = (const GMEM uint8_t *)J.src;
+    const int64_t pitch = J.src_pitch;
+    auto row_of = [&](int t) {
+        if constexpr (BM == kBmRefl) return reflect101(yin0 + t, J.H);
+        else return clampi(yin0 + t, 0, ymax);
+    };
+    auto row_in = [&](int t) { return (unsigned)(yin0 + t) <= (unsigned)ymax; };
+    auto rowp = [&](int t) { return src + (int64_t)row_of(t) * pitch; };
+
+    RawRow<PPL> raw[5];
+    v2s b3r[5][NP + 1], v1r[5][NP + 1], v2r[5][NP + 1], Pr[5][NP + 1];
+    v2s nacc[5][NP], hacc[5][NP];
+    u32 mb[PPL];   // rounded magnitudes of the last output row (LDS reads in flight)
+
+    auto fetch = [&](int t, RawRow<PPL> &r) {
+        if constexpr (ALIGNED) load_row<PPL>(r, rowp(FAST ? min(t, tlast) : t), ldx, hx);
+    };
+    auto fetch_if = [&](int t, RawRow<PPL> &r) {
+        if (FAST || t <= tlast) fetch(t, r);
+    };
+    auto window = [&](int t, RawRow<PPL> &r, v2s (&R)[NP + 4]) {
+        Win<PPL> w;
+        if constexpr (ALIGNED && BM == kBmZero) {
+            if (!row_in(t)) {
+#pragma unroll
+                for (int m = 0; m < PPL / 4; ++m) r.d[m] = 0;
+                r.hw = 0;
+            }
+        }
+        if constexpr (EDGE) apply_edge<PPL, BM>(r, efix);
+        if constexpr (ALIGNED)
+            w = finish_row<PPL, OFF, BM>(r, lane16, xo, W, fix_right, fix_left);
+        else
+            w = load_row_bytes<PPL, BM>(rowp(t), xo, W, row_in(t));
+        unpack<PPL, OFF>(w, R);
+    };
+
+    // Input slot t (ring slot S = t % 5; H = min(t, 4) earlier slots exist).
+    // With H == 4 it completes output row t - 4: E1, E2, Hp, Hm.
+    auto ingest = [&](int t, auto sc, auto hc, v2s (&E1)[NP], v2s (&E2)[NP], v2s (&Hp)[NP], v2s (&Hm)[NP]) {
+        constexpr int S = decltype(sc)::value, H = decltype(hc)::value;
+        constexpr int S1 = (S + 4) % 5, S2 = (S + 3) % 5, S3 = (S + 2) % 5, S4 = (S + 1) % 5;   // t-1 .. t-4
+        v2s R[NP + 4];
+        window(t, raw[S], R);
+        v2s hs[NP], hr[NP], ch[NP], mh[NP];
+        row_filters_bin<NP>(R, b3r[S], hs, hr, ch, mh);
+#pragma unroll
+        for (int k = 0; k < NP + 1; ++k) {
+            if constexpr (H >= 1) v1r[S1][k] = b3r[S1][k] + b3r[S][k];   // rows t-1, t
+            if constexpr (H >= 2) v2r[S2][k] = v1r[S2][k] + v1r[S1][k];  // rows t-2 .. t
+            if constexpr (H >= 3) Pr[S3][k] = v2r[S3][k] + v2r[S2][k];   // P at row t-3
+        }
+        const v2s k3 = kconst<3>(), km5 = kconst<-5>(), k6 = kconst<6>();
+#pragma unroll
+        for (int x = 0; x < NP; ++x) {
+            // Hm of output r - 2 + d takes, from row r: 3 hr - 5 hs at d = -2
+            // and +2, 3 hr at d = -1 and +1, hr + 6 hs at d = 0
+            const v2s B = hr[x] * k3;
+            const v2s A = hs[x] * km5 + B;
+            const v2s C = hs[x] * k6 + hr[x];
+            nacc[S][x] = ch[x];
+            hacc[S][x] = A;
+            if constexpr (H >= 1) {
+                nacc[S1][x] = nacc[S1][x] + mh[x];
+                hacc[S1][x] = hacc[S1][x] + B;
+            }
+            if constexpr (H >= 2) hacc[S2][x] = hacc[S2][x] + C;
+            if constexpr (H >= 3) {
+                nacc[S3][x] = nacc[S3][x] - mh[x];
+                hacc[S3][x] = hacc[S3][x] + B;
+            }
+            if constexpr (H >= 4) {
+                Hp[x] = ch[x] - nacc[S4][x];
+                Hm[x] = hacc[S4][x] + A;
+                E1[x] = Pr[S3][x + 1] - Pr[S4][x];
+                E2[x] = Pr[S4][x + 1] - Pr[S3][x];
+            }
+        }
+    };
+
+    // T of one output row and its table reads (into mb)
+    auto mag_issue = [&](const v2s (&E1)[NP], const v2s (&E2)[NP], const v2s (&Hp)[NP], const v2s (&Hm)[NP]) {
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            u32 T = sq_sat(U2(E1[j]));
+            T = sq_sat_acc(U2(E2[j]), T);
+            T = sq_sat_acc(U2(Hp[j]), T);
+            T = sq_sat_acc(U2(Hm[j]), T);
+            mb[j] = lut[T & 0xffffu];
+            mb[j + NP] = lut[T >> 16];
+        }
+    };
+
+    using P0 = std::integral_constant<int, 0>;
+    using P1 = std::integral_constant<int, 1>;
+    using P2 = std::integral_constant<int, 2>;
+    using P3 = std::integral_constant<int, 3>;
+    using P4 = std::integral_constant<int, 4>;
+
+    // step i: input slot i + 4 enters and completes output row i; the
+    // magnitudes of row i - 1 are stored (FIRST: there is none).
+    auto step = [&](int i, auto phase, auto first) {
+        constexpr int p = decltype(phase)::value;   // i % 5
+        constexpr bool FIRST = decltype(first)::value;
+        fetch_if(i + 4 + kPD, raw[(p + 4 + kPD) % 5]);
+        v2s E1[NP], E2[NP], Hp[NP], Hm[NP];
+        ingest(i + 4, std::integral_constant<int, (p + 4) % 5>{}, P4{}, E1, E2, Hp, Hm);
+        if constexpr (!FIRST) store_mag_bytes<PPL, FAST>(J, yo0 + i - 1, xo, FAST || i - 1 < nrow, mb);
+        mag_issue(E1, E2, Hp, Hm);
+        __builtin_amdgcn_sched_barrier(0);
+    };
+
+    // prologue: rows 0..4 in flight, slots 0..3 ingested, rows 5 .. 3 + kPD
+    // loaded (row t always lives in raw[t % 5]; the loads stay in row order,
+    // as in the separable sweep)
+    static_assert(kPD >= 1 && kPD <= 4, "prefetch distance must fit the 5-slot ring");
+#pragma unroll
+    for (int t = 0; t < 5; ++t) fetch_if(t, raw[t]);
+    __builtin_amdgcn_sched_barrier(0);
+    {
+        v2s d0[NP], d1[NP], d2[NP], d3[NP];   // no output yet
+        ingest(0, P0{}, P0{}, d0, d1, d2, d3);
+        __builtin_amdgcn_sched_barrier(0);
+        ingest(1, P1{}, P1{}, d0, d1, d2, d3);
+        __builtin_amdgcn_sched_barrier(0);
+        ingest(2, P2{}, P2{}, d0, d1, d2, d3);
+        __builtin_amdgcn_sched_barrier(0);
+        ingest(3, P3{}, P3{}, d0, d1, d2, d3);
+    }
+#pragma unroll
+    for (int t = 5; t < 4 + kPD; ++t) {
+        __builtin_amdgcn_sched_barrier(0);
+        fetch_if(t, raw[t % 5]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    using Yes = std::true_type;
+    using No = std::false_type;
+    step(0, P0{}, Yes{});
+
+    if constexpr (!BLOCKS) {
+        for (int i = 1; i < niter; i += 5) {
+            step(i, P1{}, No{});
+            if (i + 1 >= niter) break;
+            step(i + 1, P2{}, No{});
+            if (i + 2 >= niter) break;
+            step(i + 2, P3{}, No{});
+            if (i + 3 >= niter) break;
+            step(i + 3, P4{}, No{});
+            if (i + 4 >= niter) break;
+            step(i + 4, P0{}, No{});
+        }
+    } else {
+        // whole 5-step blocks in a loop with one exit, then the 0..4 left
+        const int nfull = 1 + (niter - 1) / 5 * 5;
+        for (int i = 1; i < nfull; i += 5) {
+            step(i, P1{}, No{});
+            step(i + 1, P2{}, No{});
+            step(i + 2, P3{}, No{});
+            step(i + 3, P4{}, No{});
+            step(i + 4, P0{}, No{});
+        }
+        if (nfull < niter) {
+            step(nfull, P1{}, No{});
+            if (nfull + 1 < niter) {
+                step(nfull + 1, P2{}, No{});
+                if (nfull + 2 < niter) {
+                    step(nfull + 2, P3{}, No{});
+                    if (nfull + 3 < niter) step(nfull + 3, P4{}, No{});
+                }
+            }
+        }
+    }
+    store_mag_bytes<PPL, FAST>(J, yo0 + niter - 1, xo, FAST || niter - 1 < nrow, mb);
+}
+
+// The four-directional operator's magnitude-only kernels take the binomial
+// form: its passes run once per input row, and it rounds on int16.  Kernels
+// that may write directional planes are bound by those stores (9 or 17
+// bytes a pixel) and keep the separable form, whose per-input-row work is
+// lighter (their row ranges are short), as do the two-directional
+// operators.
+template <int PPL, int OFF, bool ALIGNED, bool DIR, bool FAST, bool EDGE, int OPR, int BM, bool LUT, bool BLOCKS = true>
+__device__ __forceinline__ void sweep(const U8Job &J, const Sweep &g, lds_u8 *lut)
+{
+    if constexpr (binomial_form(OPR, DIR))
+        sweep4<PPL, OFF, ALIGNED, FAST, EDGE, BM, BLOCKS>(J, g, lut);
+    else
+        sweep_sep<PPL, OFF, ALIGNED, DIR, FAST, EDGE, OPR, BM, LUT, BLOCKS>(J, g, lut);
+}
+
 constexpr int kWaves = 4;   // waves per workgroup
 
 // Kernels that run two waves per SIMD (8 per CU, two 4-wave workgroups) round
 // through the table in LDS: two 64 KiB copies fit in a CU's 160 KiB.  The
 // others (three waves per SIMD) keep the square-root rounding.
 constexpr bool use_lut(int waves_per_simd) { return waves_per_simd == 2; }
+
+// LDS table bytes of a kernel: the binomial sweep rounds through the table
+// of T = S / 2, the separable one through the S table when use_lut, else
+// by square root.
+constexpr int lut_bytes(int opr, bool dir, int waves_per_simd)
+{
+    return binomial_form(opr, dir) ? kLutTSize : (use_lut(waves_per_simd) ? kLutSize : 16);
+}
+
+// Fill the kernel's table (all THREADS threads of the workgroup) and
+// synchronise the workgroup before any wave leaves.
+template <int OPR, bool DIR, int WAVES_PER_SIMD, int THREADS>
+__device__ __forceinline__ void lut_setup(uint8_t *lut)
+{
+    if constexpr (binomial_form(OPR, DIR)) {
+        lut_fill_t<THREADS>(lut);
+        __syncthreads();
+    } else if constexpr (use_lut(WAVES_PER_SIMD)) {
+        lut_fill<THREADS>(lut);
+        __syncthreads();
+    }
+}
 
 // Waves per SIMD the single-image kernel is compiled for (register budget
 // 512 / waves): 16 pixels per lane needs ~220 VGPRs (2 waves), 8 pixels per
@@ -863,12 +1245,10 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
     single_waves(PPL, OPR, ALIGNED, DIR), single_waves(PPL, OPR, ALIGNED, DIR)))) void k_u8_single(U8Job J, int nchunk)
 {
     constexpr int TW = 16 * PPL;
-    constexpr bool LUT = use_lut(single_waves(PPL, OPR, ALIGNED, DIR));
-    __shared__ __attribute__((aligned(16))) uint8_t lut[LUT ? kLutSize : 16];
-    if constexpr (LUT) {
-        lut_fill<64 * kWaves>(lut);
-        __syncthreads();   // before any wave leaves
-    }
+    constexpr int WV = single_waves(PPL, OPR, ALIGNED, DIR);
+    constexpr bool LUT = use_lut(WV);
+    __shared__ __attribute__((aligned(16))) uint8_t lut[lut_bytes(OPR, DIR, WV)];
+    lut_setup<OPR, DIR, WV, 64 * kWaves>(lut);
     lds_u8 *lutp = (lds_u8 *)lut;
     const int w = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ntxw = (J.ntx + 3) >> 2;

@@ -188,6 +188,46 @@ def test_rounding_exhaustive(oracle_mod, sobel_lib, gpu, method):
     assert np.array_equal(got, want)
 
 
+def test_rounding_of_quadruples(oracle_mod, sobel_lib, gpu):
+    """The four-directional kernels' rounding (squares of the int16 pairs
+    E1, E2, Hp, Hm summed with saturation at 32767, table of round(sqrt(2T)))
+    against the oracle's integer square root of S = 2(E1^2+E2^2+Hp^2+Hm^2):
+    every T below 2^15 + 64 reached through one component, the saturation
+    edge from each component and from their sum, the int16 extremes, random
+    quadruples around the saturation threshold, and an odd count (the last
+    value alone on its packed register)."""
+    rng = np.random.default_rng(11)
+    rows = []
+    big = np.arange(0, 182)                           # 181^2 = 32761 < 32767 < 182^2
+    for k in range(4):                                # T = v^2 from each component
+        q = np.zeros((big.size, 4), np.int64)
+        q[:, k] = big * (1 if k % 2 else -1)
+        rows.append(q)
+    t = np.arange(0, (1 << 15) + 64)                  # every T: a^2 + b^2 + c^2 + d^2 = T
+    a = np.floor(np.sqrt(t)).astype(np.int64)
+    r1 = t - a * a
+    b = np.floor(np.sqrt(r1)).astype(np.int64)
+    r2 = r1 - b * b
+    c = np.floor(np.sqrt(r2)).astype(np.int64)
+    r3 = r2 - c * c
+    d = np.floor(np.sqrt(r3)).astype(np.int64)
+    ok = r3 == d * d                                  # the greedy split leaves some T out
+    rows.append(np.stack([a, -b, c, -d], 1)[ok])
+    rows.append(np.array([[32767, 0, 0, 0], [-32768, 0, 0, 0], [0, 0, 0, -32768], [32767, 32767, 32767, 32767],
+                          [-32768, -32768, -32768, -32768], [127, 127, 0, 0], [180, 0, 0, 0], [179, 20, 0, 0],
+                          [100, 100, 100, 81], [90, 90, 90, 90], [91, 90, 90, 90], [1, 0, 0, 0]], np.int64))
+    rows.append(rng.integers(-200, 201, (200000, 4)))
+    rows.append(rng.integers(-32768, 32768, (50000, 4)))
+    q = np.concatenate(rows)
+    if q.shape[0] % 2 == 0:
+        q = q[:-1]
+    assert q.shape[0] % 2 == 1
+    S = 2 * (q ** 2).sum(1)
+    want = np.array([min(255, oracle_mod.round_sqrt(int(s))) for s in S], dtype=np.uint8)
+    got = sobel_lib.debug_round_quad(torch.from_numpy(q.astype(np.int16)).to(gpu)).cpu().numpy()
+    assert np.array_equal(got, want)
+
+
 def test_errors_raise_and_enqueue_nothing(sobel_lib, gpu):
     src = torch.zeros((10, 10), dtype=torch.uint8, device=gpu)
     with pytest.raises(ValueError):      # wrong output shape, caught before the call
