@@ -241,6 +241,29 @@ int sobel4x5_batched(const sobel4x5_image *imgs, int32_t count, int32_t border, 
 int sobel4x5_validate_batch(const sobel4x5_image *imgs, int32_t count, int32_t border);
 
 /*
+ * sobel4x5_batched_noalloc -- sobel4x5_batched for callers that cannot
+ * allocate memory: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc.  The same persistent work-queue kernel
+ * (magnitudes only, default tile shape, no autotuning, no graph), but its
+ * job table, tile table and queue counters live in a fixed device buffer of
+ * the library, one per device, held until the process ends; the call
+ * allocates no device memory (its host-side tables are per-thread buffers
+ * that keep their capacity).  It copies the tables into that buffer and
+ * launches, both on `stream`.
+ *   imgs/count/border : as for sobel4x5_batched (magnitudes only).
+ *   Limits: count <= SOBEL4X5_NOALLOC_MAX_IMAGES and at most
+ *   SOBEL4X5_NOALLOC_MAX_TILES wave-tiles (about 150 per 2048x2048 image);
+ *   a batch beyond either is SOBEL4X5_EINVAL, with nothing enqueued.
+ *   Every call on one device uses that device's one buffer, which keeps the
+ *   last call's tables: calls on one stream are ordered and safe, but calls
+ *   that overlap in time on one device (different streams not joined by
+ *   events, or different threads) race and give wrong results.
+ */
+#define SOBEL4X5_NOALLOC_MAX_IMAGES 1024
+#define SOBEL4X5_NOALLOC_MAX_TILES 65536
+int sobel4x5_batched_noalloc(const sobel4x5_image *imgs, int32_t count, int32_t border, void *stream);
+
+/*
  * Batches with per-image outputs: the calls above with `outs`, a HOST array
  * of `count` sobel4x5_outputs (copied), image i writing outs[i] -- its
  * magnitude (mag may be NULL) and/or its directional planes (dir_type, four

@@ -70,6 +70,7 @@ def _load() -> ctypes.CDLL:
         "sobel4x5_plan_info": [P] + [ctypes.POINTER(I32)] * 4,
         "sobel4x5_plan_destroy": [P],
         "sobel4x5_batched": [ctypes.POINTER(Image), I32, I32, P],
+        "sobel4x5_batched_noalloc": [ctypes.POINTER(Image), I32, I32, P],
         "sobel4x5_validate_batch": [ctypes.POINTER(Image), I32, I32],
         "sobel4x5_plan_create_ex": [ctypes.POINTER(Image), ctypes.POINTER(Outputs), I32, I32, U32, ctypes.POINTER(P)],
         "sobel4x5_batched_ex": [ctypes.POINTER(Image), ctypes.POINTER(Outputs), I32, I32, P],
@@ -407,6 +408,20 @@ def sobel4x5_batched(srcs, mags=None, border: int = BORDER_REPLICATE, *, want_ma
             mags.append(torch.empty((ho, wo), dtype=torch.uint8, device=s.device))
     arr = _images(list(srcs), list(mags), border)
     _check(lib.sobel4x5_batched(arr, len(arr), border, _stream(srcs[0])), "sobel4x5_batched")
+    return mags
+
+
+def sobel4x5_batched_noalloc(srcs, mags=None, border: int = BORDER_REPLICATE):
+    """sobel4x5_batched through the allocation-free entry point: its tables
+    live in the library's fixed device buffer (calls that overlap on one
+    device race).  Output tensors are allocated here unless `mags` is given."""
+    if mags is None:
+        mags = []
+        for s in srcs:
+            ho, wo = out_shape(s.size(0), s.size(1), border)
+            mags.append(torch.empty((ho, wo), dtype=torch.uint8, device=s.device))
+    arr = _images(list(srcs), list(mags), border)
+    _check(lib.sobel4x5_batched_noalloc(arr, len(arr), border, _stream(srcs[0])), "sobel4x5_batched_noalloc")
     return mags
 
 

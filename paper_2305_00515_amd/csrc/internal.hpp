@@ -78,6 +78,20 @@ hipError_t launch_u8_batched(const U8Job *jobs, const int4 *tiles, int32_t total
 // row blocks stacked (kind 1, in `first`).
 void batched_tiles(const U8Job &j, int32_t img, int th, std::vector<int4> &first, std::vector<int4> &last);
 
+// Allocation-free batched call (sobel4x5_batched_noalloc): the queue
+// words, the job table and the tile table of one batch live in a fixed
+// device buffer of kNoallocBytes per device, laid out as below.  The limits
+// are the public SOBEL4X5_NOALLOC_MAX_*.
+constexpr int32_t kNoallocMaxImages = 1024;
+constexpr int32_t kNoallocMaxTiles = 65536;
+constexpr size_t kNoallocJobsOff = 256;   // bytes [0, 8): queue[0], queue[1]
+constexpr size_t kNoallocTilesOff = (kNoallocJobsOff + sizeof(U8Job) * kNoallocMaxImages + 255) / 256 * 256;
+constexpr size_t kNoallocBytes = kNoallocTilesOff + sizeof(int4) * kNoallocMaxTiles;
+
+// Device address of this device's buffer (looked up once per device, with
+// that device current).
+hipError_t noalloc_scratch(void **out);
+
 // Number of workgroups of the persistent kernel that fit on the device at
 // once for shape `s` (occupancy x CUs), or 0 on error.
 int u8_persistent_grid(const U8Shape &s, int border, bool aligned, bool dir);

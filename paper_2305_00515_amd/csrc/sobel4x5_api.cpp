@@ -994,6 +994,65 @@ int sobel4x5_batched(const sobel4x5_image *imgs, int32_t count, int32_t border, 
     return sobel4x5_batched_ex(imgs, nullptr, count, border, stream);
 }
 
+static_assert(SOBEL4X5_NOALLOC_MAX_IMAGES == kNoallocMaxImages && SOBEL4X5_NOALLOC_MAX_TILES == kNoallocMaxTiles,
+              "public limits of the allocation-free batched call");
+
+int sobel4x5_batched_noalloc(const sobel4x5_image *imgs, int32_t count, int32_t border, void *stream)
+{
+    if (int rc = validate_batch(imgs, nullptr, count, border)) return rc;
+    if (count > kNoallocMaxImages)
+        return fail(SOBEL4X5_EINVAL, "%d images: the allocation-free call takes at most %d", count,
+                    kNoallocMaxImages);
+    // Tables built on the host in per-thread buffers that keep their
+    // capacity, then one copy into the fixed device buffer on `stream`.
+    const std::vector<sobel4x5_image> none;
+    const U8Shape shape = batch_default_shape(none, false);
+    thread_local std::vector<int4> tiles, tail;
+    thread_local std::vector<unsigned char> stage;
+    tiles.clear();
+    tail.clear();
+    if (stage.size() < kNoallocTilesOff) stage.resize(kNoallocTilesOff);
+    std::memset(stage.data(), 0, kNoallocJobsOff);   // queue words start at zero
+    bool aligned = true;
+    for (int32_t i = 0; i < count; ++i) {
+        const sobel4x5_image &m = imgs[i];
+        int32_t Wo, Ho;
+        out_dims(m.width, m.height, border, &Wo, &Ho);
+        U8Job j = make_job(m.src, m.width, m.height, m.src_pitch, Wo, Ho, m.mag, m.mag_pitch, nullptr, 0, 0);
+        u8_tile(j, shape);
+        aligned = aligned && u8_rows_aligned(j) && !(border == SOBEL4X5_BORDER_REFLECT101 && m.width < 3);
+        std::memcpy(stage.data() + kNoallocJobsOff + sizeof(U8Job) * i, &j, sizeof(U8Job));
+        batched_tiles(j, i, shape.th, tiles, tail);
+        if (tiles.size() + tail.size() > (size_t)kNoallocMaxTiles)
+            return fail(SOBEL4X5_EINVAL, "the batch needs more than %d wave-tiles, the allocation-free call's limit",
+                        kNoallocMaxTiles);
+    }
+    const int32_t total = (int32_t)(tiles.size() + tail.size());
+    const size_t bytes = kNoallocTilesOff + sizeof(int4) * total;
+    if (stage.size() < bytes) stage.resize(bytes);
+    std::memcpy(stage.data() + kNoallocTilesOff, tiles.data(), sizeof(int4) * tiles.size());
+    std::memcpy(stage.data() + kNoallocTilesOff + sizeof(int4) * tiles.size(), tail.data(), sizeof(int4) * tail.size());
+    void *scr = nullptr;
+    hipError_t e = guard(noalloc_scratch(&scr));
+    if (e != hipSuccess) return hip_fail(e, "looking up the fixed device buffer");
+    unsigned char *base = static_cast<unsigned char *>(scr);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // queue words and the count jobs, then the total tiles
+    if ((e = guard(hipMemcpyAsync(base, stage.data(), kNoallocJobsOff + sizeof(U8Job) * count, hipMemcpyHostToDevice,
+                                  st))) != hipSuccess ||
+        (e = guard(hipMemcpyAsync(base + kNoallocTilesOff, stage.data() + kNoallocTilesOff, sizeof(int4) * total,
+                                  hipMemcpyHostToDevice, st))) != hipSuccess)
+        return hip_fail(e, "copying the batch tables");
+    const int need = (total + 3) / 4;
+    int grid = u8_persistent_grid(shape, border, aligned, false);
+    if (grid <= 0) return fail(SOBEL4X5_EHIP, "could not query occupancy");
+    grid = std::max(1, std::min(grid, need));
+    e = guard(launch_u8_batched(reinterpret_cast<const U8Job *>(base + kNoallocJobsOff),
+                                reinterpret_cast<const int4 *>(base + kNoallocTilesOff), total,
+                                reinterpret_cast<uint32_t *>(base), border, aligned, false, shape, grid, st));
+    return e == hipSuccess ? ok() : hip_fail(e, "batched launch");
+}
+
 int sobel4x5_validate_f32(const float *src, int32_t batch, int32_t width, int32_t height, int64_t src_pitch,
                           int64_t src_bstride, int32_t border, const float *out, int64_t out_pitch,
                           int64_t out_bstride)

@@ -4,6 +4,8 @@
 
 #include "u8_sweep.hpp"
 
+#include <mutex>
+
 namespace s4x5 {
 namespace {
 
@@ -163,6 +165,31 @@ hipError_t launch_u8_batched(const U8Job *jobs, const int4 *tiles, int32_t total
     int th = s.th;
     void *args[] = {(void *)&jobs, (void *)&tiles, (void *)&total, (void *)&queue, (void *)&th};
     return hipLaunchKernel(fn, dim3(grid), dim3(64 * kWaves), args, 0, st);
+}
+
+// The fixed buffer of the allocation-free batched call.  In host code this
+// name is only a handle for hipGetSymbolAddress; kernels get the device
+// address that call returns.
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+hipError_t noalloc_scratch(void **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 int u8_persistent_grid(const U8Shape &s, int border, bool aligned, bool dir)

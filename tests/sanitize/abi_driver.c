@@ -8,6 +8,7 @@
  */
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include "sobel4x5.h"
@@ -133,6 +134,22 @@ static void check_batch(void)
         ++failures;
     }
     EXPECT(sobel4x5_plan_create(im, 3, 0, 0x80u, NULL), SOBEL4X5_EINVAL);
+    /* allocation-free batched call: host checks before any HIP call */
+    EXPECT(sobel4x5_batched_noalloc(NULL, 3, 0, NULL), SOBEL4X5_EINVAL);
+    EXPECT(sobel4x5_batched_noalloc(im, 0, 0, NULL), SOBEL4X5_EINVAL);
+    EXPECT(sobel4x5_batched_noalloc(im, 3, 7, NULL), SOBEL4X5_EINVAL);
+    {
+        const int n = SOBEL4X5_NOALLOC_MAX_IMAGES + 1;
+        sobel4x5_image *many = (sobel4x5_image *)calloc((size_t)n, sizeof *many);
+        for (int i = 0; many && i < n; ++i) {
+            many[i].src = (const uint8_t *)P(FAKE + (uintptr_t)i * 512u);
+            many[i].mag = (uint8_t *)P(FAKE + (uintptr_t)(n + i) * 512u);
+            many[i].width = many[i].height = 16;
+            many[i].src_pitch = many[i].mag_pitch = 16;
+        }
+        if (many) EXPECT(sobel4x5_batched_noalloc(many, n, 0, NULL), SOBEL4X5_EINVAL);
+        free(many);
+    }
     EXPECT(sobel4x5_plan_launch(NULL, NULL), SOBEL4X5_EINVAL);
     EXPECT(sobel4x5_plan_destroy(NULL), SOBEL4X5_EINVAL);
     char bogus[256];

@@ -29,6 +29,7 @@ hipError_t launch_fingerprint(const void *, int64_t, int64_t, int64_t, uint64_t 
 }
 hipError_t launch_round_mag(const int32_t *, uint8_t *, int64_t, int, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_round_quad(const int16_t *, uint8_t *, int64_t, hipStream_t) { return hipErrorNoDevice; }
+hipError_t noalloc_scratch(void **) { return hipErrorNoDevice; }
 hipError_t launch_f32_fwd(const F32Args &, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_f32_bwd(const F32Args &, hipStream_t) { return hipErrorNoDevice; }
 

@@ -215,3 +215,33 @@ def test_pipe_arguments_are_checked_before_any_gpu_work(sobel_lib):
     assert lib.sobel4x5_pipe_create(64, 64, 2, None) == sobel_lib.EINVAL
     assert lib.sobel4x5_pipe_run(None, None, 0, 0) == sobel_lib.EINVAL
     assert lib.sobel4x5_pipe_destroy(None) == sobel_lib.EINVAL
+
+
+def _fake_batch(api, n, w, h):
+    arr = (api.Image * n)()
+    span = w * h
+    for i in range(n):
+        arr[i].src = FAKE + 2 * i * span
+        arr[i].mag = FAKE + (2 * i + 1) * span
+        arr[i].width, arr[i].height = w, h
+        arr[i].src_pitch = arr[i].mag_pitch = w
+    return arr
+
+
+def test_noalloc_limits_are_rejected_before_any_gpu_call(sobel_lib):
+    """The allocation-free batched call takes at most
+    SOBEL4X5_NOALLOC_MAX_IMAGES images and SOBEL4X5_NOALLOC_MAX_TILES
+    wave-tiles; a batch beyond either (or an invalid one) returns EINVAL
+    from host checks alone -- this runs without a GPU."""
+    api = sobel_lib
+    f = api.lib.sobel4x5_batched_noalloc
+    assert f(_fake_batch(api, 1025, 16, 16), 1025, 0, None) == api.EINVAL       # > 1024 images
+    assert b"1024" in api.lib.sobel4x5_last_error()
+    # 8192^2 with 32-row tiles: 896 wave-tiles an image at 16 px/lane (1792
+    # at 8), so 147 of them exceed 65536 under either tile width
+    assert f(_fake_batch(api, 147, 8192, 8192), 147, 0, None) == api.EINVAL
+    assert b"65536" in api.lib.sobel4x5_last_error()
+    bad = _fake_batch(api, 4, 64, 64)
+    bad[2].mag = bad[1].src                                                    # output overlaps an input
+    assert f(bad, 4, 0, None) == api.EINVAL
+    assert f(None, 1, 0, None) == api.EINVAL
