@@ -591,9 +591,9 @@ void tune_store(const std::string &key, const U8Shape &s)
 }
 
 // Shape of a batched plan without autotuning.
-// - Magnitudes only: 16 pixels per lane and 32-row tiles on a persistent
-//   grid (a static grid is no faster: 1198 against 1200 Gpx/s on 256 mixed
-//   images).
+// - Magnitudes only: 8 pixels per lane (the binomial kernel runs three
+//   waves per SIMD there; at 16 it needs more registers than two waves per
+//   SIMD have) and 32-row tiles on a persistent grid.
 // - With directional planes, which are bound by their stores: 8 pixels per
 //   lane (the plane stores keep more values live), 4-row tiles and the
 //   static grid, one wave per tile, so that many short-lived waves keep the
@@ -604,7 +604,7 @@ void tune_store(const std::string &key, const U8Shape &s)
 U8Shape batch_default_shape(const std::vector<sobel4x5_image> &imgs, bool dir)
 {
     (void)imgs;
-    U8Shape s{dir ? 8 : 16, dir ? 4 : 32, 4};
+    U8Shape s{8, dir ? 4 : 32, 4};
     if (dir) s.waves = kStaticGrid;
     const int ppl = env_int("SOBEL4X5_BATCH_PPL", 0);
     if (ppl == 8 || ppl == 16) s.ppl = ppl;
