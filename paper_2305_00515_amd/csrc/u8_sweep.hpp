@@ -165,7 +165,7 @@ __device__ __forceinline__ u32 lut_mag(lds_u8 *lut, int S) { return lut[min((u32
 // k for 2T in (k^2 - k, k^2 + k], 255 from 2T >= 255^2 + 256 (T >= 32386),
 // so the saturated value rounds like the exact one.
 constexpr int kLutTSize = 1 << 15;
-struct MagLutT {
+struct alignas(16) MagLutT {
     uint8_t v[kLutTSize];
 };
 constexpr MagLutT make_mag_lut_t()
@@ -182,17 +182,53 @@ static_assert(kMagLutT.v[0] == 0 && kMagLutT.v[1] == 1 && kMagLutT.v[2] == 2 && 
                   kMagLutT.v[32385] == 254 && kMagLutT.v[32386] == 255 && kMagLutT.v[kLutTSize - 1] == 255,
               "rounding table of T = S/2");
 
+// The T table's copy into LDS in two halves: the loads (into registers of
+// the calling thread), then the LDS stores.  A kernel issues its first image
+// row loads together with the table loads, so that the table's trip through
+// L2 overlaps their HBM latency instead of preceding it; the caller
+// synchronises the workgroup after fill().
+template <int THREADS>
+struct LutTFill {
+    static_assert(kLutTSize % (16 * THREADS) == 0, "table split");
+    static constexpr int kPer = kLutTSize / (16 * THREADS);
+    uint4 v[kPer];
+    __device__ __forceinline__ void issue()
+    {
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) v[k] = reinterpret_cast<const uint4 *>(kMagLutT.v)[threadIdx.x + k * THREADS];
+    }
+    __device__ __forceinline__ void fill(uint8_t *lut) const
+    {
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) reinterpret_cast<uint4 *>(lut)[threadIdx.x + k * THREADS] = v[k];
+    }
+};
+
 template <int THREADS>
 __device__ __forceinline__ void lut_fill_t(uint8_t *lut)
 {
-    static_assert(kLutTSize % (16 * THREADS) == 0, "table split");
-    constexpr int kPer = kLutTSize / (16 * THREADS);
-    uint4 v[kPer];
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) v[k] = reinterpret_cast<const uint4 *>(kMagLutT.v)[threadIdx.x + k * THREADS];
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) reinterpret_cast<uint4 *>(lut)[threadIdx.x + k * THREADS] = v[k];
+    LutTFill<THREADS> f;
+    f.issue();
+    f.fill(lut);
 }
+
+// What a sweep runs around its first row loads: nothing, or the table copy
+// (issue() before the loads, finish() after them).
+struct NoPrelude {
+    __device__ __forceinline__ void issue() {}
+    __device__ __forceinline__ void finish() {}
+};
+template <int THREADS>
+struct LutPrelude {
+    LutTFill<THREADS> f;
+    uint8_t *lut;
+    __device__ __forceinline__ void issue() { f.issue(); }
+    __device__ __forceinline__ void finish()
+    {
+        f.fill(lut);
+        __syncthreads();
+    }
+};
 
 // Per 16-bit half: min(32767, a^2 + acc) for acc >= 0.  The clamp bit of
 // v_pk_mad_i16 saturates the exact a * b + c of each half to the int16
@@ -414,6 +450,11 @@ struct RawRow {
 template <int PPL>
 __device__ __forceinline__ void load_row(RawRow<PPL> &r, const GMEM uint8_t *rowp, unsigned ldx, unsigned hx)
 {
+    // Re-defining the 32-bit column offsets here (an empty asm) keeps their
+    // zero extension next to the load, so the load takes the row base from
+    // SGPRs and the offset from one VGPR (global_load ... vN, s[..]) instead
+    // of a 64-bit VGPR address built by two 64-bit adds a row.
+    asm volatile("" : "+v"(ldx), "+v"(hx));
     if constexpr (PPL == 16) {
         const gv4u v = *reinterpret_cast<const GMEM gv4u *>(rowp + ldx);
         r.d[0] = v.x; r.d[1] = v.y; r.d[2] = v.z; r.d[3] = v.w;
@@ -974,8 +1015,8 @@ __device__ __forceinline__ void store_mag_bytes(const U8Job &J, int yo, int xo, 
 // The LDS reads of one row's magnitudes are issued at the end of its step
 // and consumed by the next step's store, so their latency hides behind a
 // whole row of arithmetic.
-template <int PPL, int OFF, bool ALIGNED, bool FAST, bool EDGE, int BM, bool BLOCKS>
-__device__ __forceinline__ void sweep4(const U8Job &J, const Sweep &g, lds_u8 *lut)
+template <int PPL, int OFF, bool ALIGNED, bool FAST, bool EDGE, int BM, bool BLOCKS, class Prelude>
+__device__ __forceinline__ void sweep4(const U8Job &J, const Sweep &g, lds_u8 *lut, Prelude &pre)
 {
     static_assert(!EDGE || FAST, "edge fix-ups by mask exist for fast waves only");
     constexpr int NP = PPL / 2;
@@ -1108,8 +1149,12 @@ __device__ __forceinline__ void sweep4(const U8Job &J, const Sweep &g, lds_u8 *l
     // loaded (row t always lives in raw[t % 5]; the loads stay in row order,
     // as in the separable sweep)
     static_assert(kPD >= 1 && kPD <= 4, "prefetch distance must fit the 5-slot ring");
+    pre.issue();
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int t = 0; t < 5; ++t) fetch_if(t, raw[t]);
+    __builtin_amdgcn_sched_barrier(0);
+    pre.finish();
     __builtin_amdgcn_sched_barrier(0);
     {
         v2s d0[NP], d1[NP], d2[NP], d3[NP];   // no output yet
@@ -1173,13 +1218,17 @@ __device__ __forceinline__ void sweep4(const U8Job &J, const Sweep &g, lds_u8 *l
 // bytes a pixel) and keep the separable form, whose per-input-row work is
 // lighter (their row ranges are short), as do the two-directional
 // operators.
-template <int PPL, int OFF, bool ALIGNED, bool DIR, bool FAST, bool EDGE, int OPR, int BM, bool LUT, bool BLOCKS = true>
-__device__ __forceinline__ void sweep(const U8Job &J, const Sweep &g, lds_u8 *lut)
+template <int PPL, int OFF, bool ALIGNED, bool DIR, bool FAST, bool EDGE, int OPR, int BM, bool LUT, bool BLOCKS = true,
+          class Prelude = NoPrelude>
+__device__ __forceinline__ void sweep(const U8Job &J, const Sweep &g, lds_u8 *lut, Prelude &&pre = Prelude{})
 {
-    if constexpr (binomial_form(OPR, DIR))
-        sweep4<PPL, OFF, ALIGNED, FAST, EDGE, BM, BLOCKS>(J, g, lut);
-    else
+    if constexpr (binomial_form(OPR, DIR)) {
+        sweep4<PPL, OFF, ALIGNED, FAST, EDGE, BM, BLOCKS>(J, g, lut, pre);
+    } else {
+        pre.issue();
+        pre.finish();
         sweep_sep<PPL, OFF, ALIGNED, DIR, FAST, EDGE, OPR, BM, LUT, BLOCKS>(J, g, lut);
+    }
 }
 
 constexpr int kWaves = 4;   // waves per workgroup
@@ -1247,16 +1296,21 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
     constexpr int TW = 16 * PPL;
     constexpr int WV = single_waves(PPL, OPR, ALIGNED, DIR);
     constexpr bool LUT = use_lut(WV);
+    constexpr bool BIN = binomial_form(OPR, DIR);
     __shared__ __attribute__((aligned(16))) uint8_t lut[lut_bytes(OPR, DIR, WV)];
-    lut_setup<OPR, DIR, WV, 64 * kWaves>(lut);
+    // the binomial kernels copy their table between the first row loads and
+    // the first row (every wave of the workgroup reaches that one barrier)
+    if constexpr (!BIN) lut_setup<OPR, DIR, WV, 64 * kWaves>(lut);
     lds_u8 *lutp = (lds_u8 *)lut;
     const int w = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ntxw = (J.ntx + 3) >> 2;
-    if (w >= ntxw * nchunk) return;
     const int strip = w / nchunk, k = w % nchunk;
     const int y0 = (int)(((int64_t)k * J.Ho) / nchunk);
     const int y1 = (int)(((int64_t)(k + 1) * J.Ho) / nchunk);
-    if (y1 <= y0) return;
+    if (w >= ntxw * nchunk || y1 <= y0) {
+        if constexpr (BIN) lut_setup<OPR, DIR, WV, 64 * kWaves>(lut);
+        return;
+    }
     const int grp = (threadIdx.x >> 4) & 3;
     const int tx = strip * 4 + grp;
     Sweep g;
@@ -1270,12 +1324,18 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
     // the image); the strips at the image edges take the fast path with mask
     // fix-ups of their group halos
     const bool fast = ALIGNED && (strip * 4 + 4) * TW <= J.Wo;
-    if (fast && !g.fix_right && !g.fix_left)
-        sweep<PPL, OFF, ALIGNED, DIR, true, false, OPR, BM, LUT>(J, g, lutp);
-    else if (fast)
-        sweep<PPL, OFF, ALIGNED, DIR, true, true, OPR, BM, LUT>(J, g, lutp);
+    auto run = [&](auto pre) {
+        if (fast && !g.fix_right && !g.fix_left)
+            sweep<PPL, OFF, ALIGNED, DIR, true, false, OPR, BM, LUT>(J, g, lutp, pre);
+        else if (fast)
+            sweep<PPL, OFF, ALIGNED, DIR, true, true, OPR, BM, LUT>(J, g, lutp, pre);
+        else
+            sweep<PPL, OFF, ALIGNED, DIR, false, false, OPR, BM, LUT>(J, g, lutp, pre);
+    };
+    if constexpr (BIN)
+        run(LutPrelude<64 * kWaves>{{}, lut});
     else
-        sweep<PPL, OFF, ALIGNED, DIR, false, false, OPR, BM, LUT>(J, g, lutp);
+        run(NoPrelude{});
 }
 
 
