@@ -243,10 +243,10 @@ int sobel4x5_validate_batch(const sobel4x5_image *imgs, int32_t count, int32_t b
 /*
  * sobel4x5_batched_noalloc -- sobel4x5_batched for callers that cannot
  * allocate memory: code under HIP graph capture, tight serving loops and
- * harnesses that forbid hipMalloc.  The same persistent work-queue kernel
- * (magnitudes only, default tile shape, no autotuning, no graph), but its
- * job table, tile table and queue counters live in a fixed device buffer of
- * the library, one per device, held until the process ends; the call
+ * harnesses that forbid hipMalloc.  The same batched kernel (magnitudes
+ * only, the default tile shape and grid form, no autotuning, no graph), but
+ * its job table, tile table and queue counters live in a fixed device buffer
+ * of the library, one per device, held until the process ends; the call
  * allocates no device memory (its host-side tables are per-thread buffers
  * that keep their capacity).  It copies the tables into that buffer and
  * launches, both on `stream`.

@@ -61,17 +61,21 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
     constexpr int TW = 16 * PPL;
     constexpr int WV = single_waves(PPL, kOp4x5, ALIGNED, DIR);
     constexpr bool LUT = use_lut(WV);
+    constexpr bool BIN = binomial_form(kOp4x5, DIR);
     __shared__ __attribute__((aligned(16))) uint8_t lut[lut_bytes(kOp4x5, DIR, WV)];
-    lut_setup<kOp4x5, DIR, WV, 64 * kWaves>(lut);
     lds_u8 *lutp = (lds_u8 *)lut;
     const int lane = threadIdx.x & 63;
-    // one tile of the table: returns false when it has no rows
-    auto run_tile = [&](int t) __attribute__((always_inline)) {
+    // one tile of the table; `pre` runs around its first row loads
+    auto run_tile = [&](int t, auto pre) __attribute__((always_inline)) {
         const int4 ti = tiles[t];
         const U8Job J = jobs[ti.x];
         Sweep g = batch_geometry(J, ti, PPL, TH);
         g.fix_left = g.fix_left && OFF == 0;
-        if (g.niter <= 0) return;
+        if (g.niter <= 0) {
+            pre.issue();
+            pre.finish();
+            return;
+        }
         // fast: every group has its full rows, every lane's block and output
         // inside the image
         bool fast;
@@ -83,24 +87,35 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
             fast = ALIGNED && full && (ti.z + 1) * TW <= J.Wo;
         }
         if (fast && !g.fix_right && !g.fix_left)
-            sweep<PPL, OFF, ALIGNED, DIR, true, false, kOp4x5, BM, LUT, false>(J, g, lutp);
+            sweep<PPL, OFF, ALIGNED, DIR, true, false, kOp4x5, BM, LUT, false>(J, g, lutp, pre);
         else if (fast)
-            sweep<PPL, OFF, ALIGNED, DIR, true, true, kOp4x5, BM, LUT, false>(J, g, lutp);
+            sweep<PPL, OFF, ALIGNED, DIR, true, true, kOp4x5, BM, LUT, false>(J, g, lutp, pre);
         else
-            sweep<PPL, OFF, ALIGNED, DIR, false, false, kOp4x5, BM, LUT, false>(J, g, lutp);
+            sweep<PPL, OFF, ALIGNED, DIR, false, false, kOp4x5, BM, LUT, false>(J, g, lutp, pre);
     };
     if (queue == nullptr) {
-        // static form: wave w of the grid takes tile w, no queue
+        // static form: wave w of the grid takes tile w, no queue; the
+        // binomial kernel copies its table while the tile's first rows load
+        // (every wave of the workgroup reaches that one barrier)
         const int t = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        if (t < total) run_tile(t);
+        if constexpr (BIN) {
+            if (t < total)
+                run_tile(t, LutPrelude<64 * kWaves>{{}, lut});
+            else
+                lut_setup<kOp4x5, DIR, WV, 64 * kWaves>(lut);
+        } else {
+            lut_setup<kOp4x5, DIR, WV, 64 * kWaves>(lut);
+            if (t < total) run_tile(t, NoPrelude{});
+        }
         return;
     }
+    lut_setup<kOp4x5, DIR, WV, 64 * kWaves>(lut);
     for (;;) {
         u32 tv = 0;
         if (lane == 0) tv = atomicAdd(&queue[0], 1u);
         const int t = __builtin_amdgcn_readfirstlane((int)tv);
         if (t >= total) break;
-        run_tile(t);
+        run_tile(t, NoPrelude{});
     }
     if (lane == 0) {
         __threadfence();
