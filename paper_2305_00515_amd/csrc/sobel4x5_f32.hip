@@ -193,6 +193,31 @@ __device__ __forceinline__ void run_steps(int T, Step &step)
     }
 }
 
+// Steps t0 .. t1-1 (t0 a multiple of five, so the ring phase of step t is
+// t % 5), in blocks of five with a single exit, then the rest.
+template <class Step>
+__device__ __forceinline__ void run_steps_from(int t0, int t1, Step &step)
+{
+    const int nfull = t0 + (t1 - t0) / 5 * 5;
+    for (int t = t0; t < nfull; t += 5) {
+        step(t, Ph<0>{});
+        step(t + 1, Ph<1>{});
+        step(t + 2, Ph<2>{});
+        step(t + 3, Ph<3>{});
+        step(t + 4, Ph<4>{});
+    }
+    if (nfull < t1) {
+        step(nfull, Ph<0>{});
+        if (nfull + 1 < t1) {
+            step(nfull + 1, Ph<1>{});
+            if (nfull + 2 < t1) {
+                step(nfull + 2, Ph<2>{});
+                if (nfull + 3 < t1) step(nfull + 3, Ph<3>{});
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- forward
 // Wave (image b, strip s, chunk k): output columns [s*124, s*124+124),
 // output rows [o0, o1).  Lane l holds output columns s*124 - 2 + 2l + {0, 1}
@@ -219,10 +244,23 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_fwd(F32Args a, int 
     char *dst = reinterpret_cast<char *>(a.out) + (int64_t)b * a.out_bstride;
     const int64_t oa = (int64_t)(ox < 0 ? 0 : ox) * 4;
     const int r0 = o0 + OFF - 2;
+    // wave-uniform: every lane's column pair inside the image, 8-byte rows
+    // (a pair is one 8-byte load)
+    const int cx0 = s * kOwnF - kHaloF + OFF;                 // input column of lane 0's element a
+    const bool vec = cx0 >= 0 && cx0 + 128 <= a.W &&
+                     ((reinterpret_cast<uintptr_t>(src) | (uintptr_t)a.src_pitch) & 7u) == 0;
+    // both kept columns stored with one 8-byte store
+    const bool vst = keep_a && keep_b && ((reinterpret_cast<uintptr_t>(dst) | (uintptr_t)a.out_pitch) & 7u) == 0;
     auto ld = [&](int t) {
         const int r = r0 + t;
         const char *row = src + (int64_t)edge_index<BM>(r, a.H) * a.src_pitch;
-        F2 v{*reinterpret_cast<const float *>(row + xa), *reinterpret_cast<const float *>(row + xb)};
+        F2 v;
+        if (vec) {
+            const float2 w = *reinterpret_cast<const float2 *>(row + xa);
+            v = F2{w.x, w.y};
+        } else {
+            v = F2{*reinterpret_cast<const float *>(row + xa), *reinterpret_cast<const float *>(row + xb)};
+        }
         if constexpr (BM == kZero) {
             const bool rin = r >= 0 && r < a.H;
             v = F2{rin && ina ? v.a : 0.f, rin && inb ? v.b : 0.f};
@@ -257,8 +295,13 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_fwd(F32Args a, int 
         F2 Gy, Gp;
         hcombine(vr, vs, Gy, Gp);
         float *row = reinterpret_cast<float *>(dst + (int64_t)(o0 + t - 4) * a.out_pitch + oa);
-        if (keep_a) row[0] = mag_of(Gx.a, Gy.a, Gp.a, Gm.a);
-        if (keep_b) row[1] = mag_of(Gx.b, Gy.b, Gp.b, Gm.b);
+        const float ma = mag_of(Gx.a, Gy.a, Gp.a, Gm.a), mb = mag_of(Gx.b, Gy.b, Gp.b, Gm.b);
+        if (vst) {
+            *reinterpret_cast<float2 *>(row) = float2{ma, mb};
+        } else {
+            if (keep_a) row[0] = ma;
+            if (keep_b) row[1] = mb;
+        }
     };
     run_steps(T, step);
 }
@@ -313,16 +356,32 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
     const char *gr = reinterpret_cast<const char *>(a.grad) + (int64_t)b * a.g_bstride;
     char *dst = reinterpret_cast<char *>(a.out) + (int64_t)b * a.out_bstride + (int64_t)(c < 0 ? 0 : c) * 4;
     const int c0 = s * kOwnB - kHaloB;                        // column of lane 0's element a
+    // both kept columns stored with one 8-byte store (c is even)
+    const bool vst = keep_a && keep_b && c >= 0 &&
+                     ((reinterpret_cast<uintptr_t>(a.out) | (uintptr_t)a.out_pitch | (uintptr_t)a.out_bstride) & 7u) == 0;
     // input rows X0-4 .. X1+3 give the adjoint rows [X0, X1); at the top and
     // bottom of the image, where padded rows fold back, two more rows on
     // that side give the padded rows -2, -1 and H, H+1
     const int r0 = X0 - ((kFold && X0 == 0) ? 6 : 4);
     const int T = X1 + ((kFold && X1 == a.H) ? 6 : 4) - r0;
 
+    // Wave-uniform: every lane's column pair lies inside the image (and, for
+    // grad, inside the output) and the rows are 8-byte aligned, so a pair is
+    // one 8-byte load (xb = xa + 4, gb = ga + 4, all lanes centred).
+    const bool vecx = c0 >= 0 && c0 + 128 <= a.W &&
+                      ((reinterpret_cast<uintptr_t>(src) | (uintptr_t)a.src_pitch) & 7u) == 0;
+    const bool vecg = c0 - OFF >= 0 && c0 + 128 - OFF <= a.Wo &&
+                      ((reinterpret_cast<uintptr_t>(gr) | (uintptr_t)a.g_pitch) & 7u) == 0;
     auto ldx = [&](int t) {
         const int r = r0 + t;
         const char *row = src + (int64_t)edge_index<BM>(r, a.H) * a.src_pitch;
-        F2 v{*reinterpret_cast<const float *>(row + xa), *reinterpret_cast<const float *>(row + xb)};
+        F2 v;
+        if (vecx) {
+            const float2 w = *reinterpret_cast<const float2 *>(row + xa);
+            v = F2{w.x, w.y};
+        } else {
+            v = F2{*reinterpret_cast<const float *>(row + xa), *reinterpret_cast<const float *>(row + xb)};
+        }
         if constexpr (BM == kZero) {
             const bool rin = r >= 0 && r < a.H;
             v = F2{rin && ina ? v.a : 0.f, rin && inb ? v.b : 0.f};
@@ -335,8 +394,14 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
         F2 v{0.f, 0.f};
         if (o >= 0 && o < a.Ho) {
             const char *row = gr + (int64_t)o * a.g_pitch;
-            v = F2{*reinterpret_cast<const float *>(row + ga), *reinterpret_cast<const float *>(row + gb)};
+            if (vecg) {
+                const float2 w = *reinterpret_cast<const float2 *>(row + ga);
+                v = F2{w.x, w.y};
+            } else {
+                v = F2{*reinterpret_cast<const float *>(row + ga), *reinterpret_cast<const float *>(row + gb)};
+            }
         }
+        if (vecg) return v;
         return F2{oc_a ? v.a : 0.f, oc_b ? v.b : 0.f};
     };
 
@@ -347,7 +412,7 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
 #pragma unroll
     for (int i = 0; i < 5; ++i)
         X[i] = HR[i] = HS[i] = WX[i] = WM[i] = WY[i] = WP[i] = pfx[i] = pfg[i] = F2{0.f, 0.f};
-    constexpr int PD = 3;
+    constexpr int PD = 3;   // rows loaded ahead (measured: 2 is 9% slower, 4 no faster)
     // prologue loads in row order (the loop's first steps consume them)
 #pragma unroll
     for (int t = 0; t < PD; ++t) {
@@ -399,12 +464,19 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
             }
         }
         float *p = reinterpret_cast<float *>(dst + (int64_t)row * a.out_pitch);
-        if (keep_a) p[0] = v.a;
-        if (keep_b) p[1] = v.b;
+        if (vst) {
+            *reinterpret_cast<float2 *>(p) = float2{v.a, v.b};
+        } else {
+            if (keep_a) p[0] = v.a;
+            if (keep_b) p[1] = v.b;
+        }
     };
 
-    auto step = [&](int t, auto phase) __attribute__((always_inline)) {
+    // INTERIOR: a row of P that is one of the wave's own rows and no padded
+    // row folds onto (rows 3 .. H-4 under a folding rule): stored as is.
+    auto step = [&](int t, auto phase, auto interior) __attribute__((always_inline)) {
         constexpr int p = decltype(phase)::value;
+        constexpr bool INTERIOR = decltype(interior)::value;
         // input rows t-4 .. t live in slots (p+1)%5 .. p
         constexpr int s0 = (p + 1) % 5, s1 = (p + 2) % 5, s2 = (p + 3) % 5, s3 = (p + 4) % 5, s4 = p;
         pfx[(p + PD) % 5] = ldx(min(t + PD, T - 1));
@@ -453,6 +525,10 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
         const F2 P{(Q0.a + Qp1.b) + from_left(Qm2.a + Qm1.b) + from_right(Qp2.a),
                    (Qm1.a + Q0.b) + from_left(Qm2.b) + from_right(Qp1.a + Qp2.b)};
         const int pr = r0 + t - 4;               // padded row of P
+        if constexpr (INTERIOR) {
+            store(pr, P);
+            return;
+        }
         if (pr < X0 - 2 || pr >= X1 + 2) return;  // warm-up and rows of other waves
         if constexpr (!kFold) {                   // VALID, ZERO: nothing folds back
             if (pr >= X0 && pr < X1) store(pr, P);
@@ -512,7 +588,20 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
                 store(pr, v);
         }
     };
-    run_steps(T, step);
+    // steps whose P row is interior, [ta, tb) with ta a multiple of five
+    // (the ring phase stays t % 5), run without the row checks; the others
+    // take the general step
+    const int plo = kFold ? max(X0, 3) : X0, phi = kFold ? min(X1, a.H - 3) : X1;
+    int ta = min(T, (plo - r0 + 4 + 4) / 5 * 5);
+    const int tb = max(ta, phi - r0 + 4);
+    using Gen = std::false_type;
+    using Int = std::true_type;
+    auto gen = [&](int t, auto ph) __attribute__((always_inline)) { step(t, ph, Gen{}); };
+    auto mid = [&](int t, auto ph) __attribute__((always_inline)) { step(t, ph, Int{}); };
+    run_steps_from(0, ta, gen);
+    const int tm = ta + (tb - ta) / 5 * 5;
+    run_steps_from(ta, tm, mid);
+    run_steps_from(tm, T, gen);
     if constexpr (kFold && BM == kRefl) {
         if (X1 == a.H) {                           // the held rows, with H and H+1 added
             if (a.H - 3 >= X0) store(a.H - 3, hold0);
