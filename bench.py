@@ -355,6 +355,7 @@ def bench_f32(torch, api, synth, dev, steps, warmup):
     gm = torch.full_like(x, 1.0 / x.numel())
     dx = torch.empty_like(x)
     k = max(5, steps // 10)
+    clock_warmup(torch, lambda i: api.sobel4x5_f32_bwd(x, gm, out=dx), max_s=4.0)
     ms_f = time_launches(torch, lambda i: api.sobel4x5_f32_fwd(x, out=M), k, max(3, warmup))
     ms_b = time_launches(torch, lambda i: api.sobel4x5_f32_bwd(x, gm, out=dx), k, max(3, warmup // 2))
     px = B * H * W
@@ -433,9 +434,10 @@ def bench_copy(torch, api, dev, steps):
 #            WRITE_SIZE (KiB per dispatch), each scaled by what the same
 #            counter reads for the plain copy kernel (sobel4x5_debug_copy) of
 #            known size (profiles/k_u8_single_8192x8192_mag_u8.md);
-#   valu:    VALU issue slots per output pixel (SQ_INSTS_VALU per pixel from
-#            the same profile, counting the half-rate square root twice).
-U8_PROFILE = {"src_sha256": "f32f9ced96bc6bdf", "traffic_bytes": 145204014, "valu_slots_per_px": (1791 + 80) / 80.0}
+#   valu:    VALU instructions per output pixel (SQ_INSTS_VALU x 64 / pixels
+#            from the same profile; the kernel has no transcendental
+#            instruction, so each is one issue slot).
+U8_PROFILE = {"src_sha256": "ae4742c5983b88a5", "traffic_bytes": 145347379, "valu_slots_per_px": 21434880 * 64 / 8192.0 ** 2}
 
 
 # Sources k_u8_single is compiled from (the hash covers them in this order);
@@ -544,7 +546,7 @@ def main():
                        "hot_same_buffer_ms": round(r["hot_ms"], 5), "per_launch_us": r["per_launch_us"]},
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": u8_profile("traffic_bytes"),
-                         "kernel": "k_u8_single<16,replicate,aligned,mag-only>",
+                         "kernel": "k_u8_single<8,replicate,aligned,mag-only>",
                          "alg_bytes_per_launch": r["alg_bytes"], "valu": valu},
         })
     if want("copy"):

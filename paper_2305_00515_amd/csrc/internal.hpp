@@ -38,6 +38,7 @@ struct U8Shape {
     int wpg;        // waves per workgroup (4)
     int waves = 0;  // single-image kernel: waves to launch (0 = all resident waves)
     int min_rows = 2;   // single-image kernel: fewest output rows per wave (small images are latency-bound)
+    bool sep = false;   // four-directional magnitudes in the separable form (the kernel that also serves planes)
 };
 
 // True when the fast (vector-load) kernel may read this image: 16-byte

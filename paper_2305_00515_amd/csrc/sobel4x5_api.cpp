@@ -216,6 +216,21 @@ U8Shape default_shape(int32_t Wo, int32_t Ho, int32_t dir_type, int32_t op = SOB
     const int64_t strips16 = (Wo + 1023) / 1024;
     const bool fills = strips16 * (Ho / 2) >= 8 * (int64_t)device_cus();
     s.ppl = (fills && dir_type == SOBEL4X5_DIR_NONE && op != SOBEL4X5_OP_4DIR_5X5) ? 16 : 8;
+    // The binomial form does most of its work once per input row, so a
+    // wave that gets few rows pays heavily for the 4 rows above its range:
+    // below 8 rows per wave (one round of 12 waves per CU over 512-column
+    // strips) the four-directional magnitude takes the separable form
+    // (graph replay: 512^2 3.48 against 4.32 us, 1920x1080 6.92 against
+    // 9.33, 3840x2160 12.6 against 13.9; from 4096^2 on the binomial form
+    // wins: 17.4 against 18.1), with 4-row minimum ranges from 2048 rows on.
+    if (op == SOBEL4X5_OP_4DIR_5X5 && dir_type == SOBEL4X5_DIR_NONE) {
+        const int64_t strips8 = (Wo + 511) / 512;
+        const int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(12 * (int64_t)device_cus() / strips8, Ho / 2));
+        if (Ho < 8 * nchunk) {
+            s.sep = true;
+            if (Ho >= 2048) s.min_rows = 4;
+        }
+    }
     const int ppl = env_int("SOBEL4X5_U8_PPL", 0);
     if (ppl == 8 || ppl == 16) s.ppl = ppl;
     s.th = 32;
@@ -231,6 +246,8 @@ U8Shape default_shape(int32_t Wo, int32_t Ho, int32_t dir_type, int32_t op = SOB
     if (waves > 0) s.waves = waves;
     const int mr = env_int("SOBEL4X5_U8_MIN_ROWS", 0);
     if (mr >= 1 && mr <= 64) s.min_rows = mr;
+    const int sep = env_int("SOBEL4X5_U8_SEP", -1);
+    if (sep == 0 || sep == 1) s.sep = sep == 1;
     return s;
 }
 

@@ -63,8 +63,10 @@ hipError_t launch_single_t(const U8Job &j, const U8Shape &s, hipStream_t st)
 template <int PPL, int OFF, int OPR, int BM>
 hipError_t launch_single_d(const U8Job &j, const U8Shape &s, hipStream_t st)
 {
-    return j.dir_type ? launch_single_t<PPL, OFF, true, OPR, BM>(j, s, st)
-                      : launch_single_t<PPL, OFF, false, OPR, BM>(j, s, st);
+    // the kernels compiled with planes also write magnitudes alone (dir_type 0),
+    // in the separable form
+    return (j.dir_type || s.sep) ? launch_single_t<PPL, OFF, true, OPR, BM>(j, s, st)
+                                 : launch_single_t<PPL, OFF, false, OPR, BM>(j, s, st);
 }
 
 // Single-image launch of operator OPR under border rule BM; with kBmRep,

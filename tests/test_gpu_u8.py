@@ -27,7 +27,7 @@ def dev_out(h, w, dev, dtype=torch.uint8, pitch_elems=None, sentinel=0x5A):
 def run(api, img, dev, border=0, dir_type=0, pitch=None, offset=0, mag_pitch=None):
     src = dev_image(img, dev, pitch, offset)
     h, w = img.shape
-    ho, wo = (h, w) if border == 0 else (h - 4, w - 4)
+    ho, wo = (h - 4, w - 4) if border == 1 else (h, w)  # only VALID shrinks
     mag, mag_flat = dev_out(ho, wo, dev, pitch_elems=mag_pitch)
     dirs = None
     if dir_type:
@@ -81,6 +81,23 @@ def test_size_sweep(oracle_mod, sobel_lib, gpu, h, w):
     check(oracle_mod, sobel_lib, img, gpu, 0, 2)
     if h >= 5 and w >= 5:
         check(oracle_mod, sobel_lib, img, gpu, 1, 1)
+
+
+# Four-directional magnitudes alone take the binomial form or the separable
+# form by image size; SOBEL4X5_U8_SEP forces either one, so both stay
+# covered on small and ragged geometries whatever the size rule picks.
+@pytest.mark.parametrize("sep", ["0", "1"])
+@pytest.mark.parametrize("h,w", [(1, 1), (3, 3), (5, 5), (7, 15), (17, 63), (63, 64), (65, 127),
+                                 (129, 255), (20, 257), (300, 4099), (1080, 1920)])
+def test_both_magnitude_forms(oracle_mod, sobel_lib, gpu, monkeypatch, sep, h, w):
+    monkeypatch.setenv("SOBEL4X5_U8_SEP", sep)
+    img = synth.rect_image(h, w, h * 31 + w)
+    for border in (0, 1, 2, 3):
+        if border == 1 and (h < 5 or w < 5):
+            continue
+        mag, _, _ = run(sobel_lib, img, gpu, border, 0)
+        om, _ = oracle_mod.sobel_u8(img, border, want_dir=False)
+        assert np.array_equal(mag, om), "sep=%s border=%d: %d pixels differ" % (sep, border, int((mag != om).sum()))
 
 
 @pytest.mark.parametrize("w", [61, 200, 1001])
