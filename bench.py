@@ -8,7 +8,7 @@ persistent launch vs per-image launches, fp32 forward+backward, the size /
 output-type sweep) are reported in extra keys of the same JSON line.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W]
-                [--only u8,copy,sweep,ops,borders,batched,f32,weighted,pipe]
+                [--only u8,copy,sweep,ops,borders,batched,f32,weighted,pipe,mfma]
                 [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -43,12 +43,12 @@ def parse():
     # per 8192^2 launch), so the default warm-up covers them
     p.add_argument("--warmup", type=int, default=400)
     p.add_argument("--only", default=None,
-                   help="comma-separated subset of: u8, copy, sweep, ops, borders, batched, f32, weighted, pipe")
+                   help="comma-separated subset of: u8, copy, sweep, ops, borders, batched, f32, weighted, pipe, mfma")
     p.add_argument("--no-cpu-baseline", action="store_true")
     a = p.parse_args()
     if a.only is not None:
         a.only = set(x.strip() for x in a.only.split(",") if x.strip())
-        bad = a.only - {"u8", "copy", "sweep", "ops", "borders", "batched", "f32", "weighted", "pipe"}
+        bad = a.only - {"u8", "copy", "sweep", "ops", "borders", "batched", "f32", "weighted", "pipe", "mfma"}
         if bad:
             p.error("unknown --only part(s): %s" % ", ".join(sorted(bad)))
     return a
@@ -200,6 +200,47 @@ def bench_sweep(torch, api, synth, dev, steps, warmup):
                                         "bytes_per_px": per // px}
             del srcs, outs, base
             torch.cuda.empty_cache()
+    return out
+
+
+def bench_mfma(torch, api, synth, dev, steps, warmup):
+    """The headline launch in its matrix-core form (SOBEL4X5_U8_MFMA=1, the
+    5x5 responses as banded int8 products) beside the default form, on the
+    same rotating buffers after the same clock warm-up; the matrix-core form
+    at 1, 2 and 4 rounds of resident waves (SOBEL4X5_U8_WAVES)."""
+    img = synth.rect_image(N, N, 3)
+    nsets = max(2, ROTATE_BYTES // (2 * N * N))
+    srcs, mags = image_sets(torch, img, dev, nsets)
+    px = N * N
+    out = {}
+    saved = {k: os.environ.get(k) for k in ("SOBEL4X5_U8_MFMA", "SOBEL4X5_U8_WAVES")}
+    try:
+        for name, flag, waves in (("default", "0", None), ("matrix_cores_1_round", "1", 4096),
+                                  ("matrix_cores_2_rounds", "1", 8192), ("matrix_cores_4_rounds", "1", 16384)):
+            os.environ["SOBEL4X5_U8_MFMA"] = flag
+            if waves is None:
+                os.environ.pop("SOBEL4X5_U8_WAVES", None)
+            else:
+                os.environ["SOBEL4X5_U8_WAVES"] = str(waves)
+            step = lambda i: api.sobel4x5_u8(srcs[i % nsets], mag=mags[i % nsets])
+            clock_warmup(torch, step, max_s=3.0)
+            ms = time_launches(torch, step, steps, warmup)
+            out[name] = {"us": round(ms * 1e3, 2), "gpx_per_s": round(px / (ms * 1e-3) / 1e9, 2)}
+        # both forms write the same bytes
+        os.environ["SOBEL4X5_U8_MFMA"] = "1"
+        api.sobel4x5_u8(srcs[0], mag=mags[0])
+        os.environ["SOBEL4X5_U8_MFMA"] = "0"
+        api.sobel4x5_u8(srcs[0], mag=mags[1])
+        torch.cuda.synchronize()
+        out["outputs_equal"] = bool(torch.equal(mags[0], mags[1]))
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    del srcs, mags
+    torch.cuda.empty_cache()
     return out
 
 
@@ -570,6 +611,9 @@ def main():
     if want("pipe"):
         log("host pipeline 64 x 3840x2160")
         line["pipe"] = bench_pipe(torch, api, synth, dev, args.steps)
+    if want("mfma"):
+        log("matrix-core form of the headline launch")
+        line["mfma"] = bench_mfma(torch, api, synth, dev, args.steps, args.warmup)
     if want("f32"):
         log("fp32 32x1024^2 fwd+bwd")
         line["f32"] = bench_f32(torch, api, synth, dev, args.steps, args.warmup)

@@ -19,7 +19,8 @@ LIB = PKG / "libsobel4x5.so"
 ARCH = os.environ.get("SOBEL4X5_ARCH", "gfx950")
 
 SOURCES = ["sobel4x5_api.cpp", "sobel4x5_u8.hip", "sobel4x5_u8_border.hip", "sobel4x5_batched.hip",
-           "sobel_2dir_u8.hip", "sobel_2dir_u8_border.hip", "sobel4x5_f32.hip", "sobel4x5_weighted.hip"]
+           "sobel_2dir_u8.hip", "sobel_2dir_u8_border.hip", "sobel4x5_f32.hip", "sobel4x5_weighted.hip",
+           "sobel4x5_mfma.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -55,6 +55,11 @@ void u8_tile(U8Job &j, const U8Shape &s);
 hipError_t launch_u8_single(const U8Job &j, int border, const U8Shape &s, hipStream_t stream);
 hipError_t launch_u8_single_zr(const U8Job &j, int border, const U8Shape &s, hipStream_t stream);
 
+// Magnitudes alone of the four-directional operator on the matrix cores
+// (u8_mfma.hpp): 32 x 128 output tiles, `waves` waves in all (0 = four
+// rounds of resident waves).  `border`: the public code.
+hipError_t launch_u8_mfma(const U8Job &j, int border, int waves, hipStream_t stream);
+
 // Two-directional operators on the single-image sweep: op 1 = the 0 / 90 deg
 // filters of the 5x5 operator, op 2 = the 3x3 pair (VALID: off = 1).  The
 // job's Wo, Ho and tiling are those of the operator's own border rule.

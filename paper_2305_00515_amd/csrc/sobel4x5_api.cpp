@@ -863,6 +863,10 @@ int sobel4x5_u8(const uint8_t *src, int32_t width, int32_t height, int64_t src_p
                        out->dir_type ? out->dir : nullptr, out->dir_pitch, out->dir_type);
     const U8Shape s = default_shape(Wo, Ho, out->dir_type);
     u8_tile(j, s);
+    if (out->dir_type == SOBEL4X5_DIR_NONE && out->mag && env_int("SOBEL4X5_U8_MFMA", 0) == 1) {
+        hipError_t e = guard(launch_u8_mfma(j, border, env_int("SOBEL4X5_U8_WAVES", 0), static_cast<hipStream_t>(stream)));
+        return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_u8 launch");
+    }
     hipError_t e = guard(launch_u8_single(j, border, s, static_cast<hipStream_t>(stream)));
     return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_u8 launch");
 }
