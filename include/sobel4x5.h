@@ -226,6 +226,26 @@ int sobel4x5_plan_launch(sobel4x5_plan plan, void *stream);
 int sobel4x5_plan_info(sobel4x5_plan plan, int32_t *px_per_lane, int32_t *rows_per_tile,
                        int32_t *waves_per_group, int32_t *grid);
 
+/*
+ * sobel4x5_debug_plan_claims -- work-queue check: one launch of the plan that
+ * also counts, per tile of its work table, how many waves took that tile.
+ *   plan     : a plan from sobel4x5_plan_create(_ex).
+ *   claims   : device array of `capacity` uint32 counters, or NULL to only
+ *              query the tile count.
+ *   capacity : counters in `claims`; must be >= *ntiles (EINVAL otherwise).
+ *   ntiles   : receives the plan's tile count (always, also with claims NULL).
+ *   stream   : HIP stream.
+ * Clears claims[0 .. ntiles) and launches the plan's kernel once, directly
+ * (not through its graph), on `stream`; the outputs are written as by
+ * sobel4x5_plan_launch.  In a correct launch every counter ends at 1 (none
+ * skipped, none taken twice), in the persistent and in the static grid form.
+ * Must not overlap another launch of the same plan.  For tests and
+ * diagnostics: it checks the batched work queue, which is this library's own
+ * scheduling of many images and has no counterpart in the paper.
+ */
+int sobel4x5_debug_plan_claims(sobel4x5_plan plan, uint32_t *claims, int64_t capacity, int64_t *ntiles,
+                               void *stream);
+
 /* Free the plan (device memory, graph).  Waits for nothing: the caller must
  * make sure no launch of it is still running. */
 int sobel4x5_plan_destroy(sobel4x5_plan plan);

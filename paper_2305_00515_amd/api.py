@@ -68,6 +68,7 @@ def _load() -> ctypes.CDLL:
         "sobel4x5_plan_create": [ctypes.POINTER(Image), I32, I32, U32, ctypes.POINTER(P)],
         "sobel4x5_plan_launch": [P, P],
         "sobel4x5_plan_info": [P] + [ctypes.POINTER(I32)] * 4,
+        "sobel4x5_debug_plan_claims": [P, P, I64, ctypes.POINTER(I64), P],
         "sobel4x5_plan_destroy": [P],
         "sobel4x5_batched": [ctypes.POINTER(Image), I32, I32, P],
         "sobel4x5_batched_noalloc": [ctypes.POINTER(Image), I32, I32, P],
@@ -374,6 +375,17 @@ class Plan:
         _check(lib.sobel4x5_plan_info(self._h, *[ctypes.byref(v) for v in vals]), "sobel4x5_plan_info")
         return dict(zip(("px_per_lane", "rows_per_tile", "waves_per_group", "grid"),
                         (v.value for v in vals)))
+
+    def claims(self):
+        """One launch that also counts how many waves took each tile of the
+        work table (sobel4x5_debug_plan_claims): an int32 tensor of one count
+        per tile, all 1 when no tile was skipped or taken twice."""
+        n = ctypes.c_int64()
+        _check(lib.sobel4x5_debug_plan_claims(self._h, None, 0, ctypes.byref(n), None), "sobel4x5_debug_plan_claims")
+        c = torch.zeros(max(1, n.value), dtype=torch.int32, device=self.device)
+        _check(lib.sobel4x5_debug_plan_claims(self._h, c.data_ptr(), c.numel(), ctypes.byref(n),
+                                              _stream(self._keep[0][0])), "sobel4x5_debug_plan_claims")
+        return c[: n.value]
 
     def close(self) -> None:
         if getattr(self, "_h", None):

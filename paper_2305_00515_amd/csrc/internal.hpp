@@ -73,9 +73,11 @@ hipError_t launch_u8_2dir_zr(const U8Job &j, int op, int border, const U8Shape &
 // (batched_tiles); `queue` (device, 2 words, zero before the first launch)
 // is the work counter and the exit counter, reset by the last wave to
 // finish.  `border`: the public code; `dir`: some job asks for directional
-// planes.
+// planes.  `claims` (device, `total` counters, or null): each tile's counter
+// gains one for every wave that takes the tile.
 hipError_t launch_u8_batched(const U8Job *jobs, const int4 *tiles, int32_t total, uint32_t *queue, int border,
-                             bool aligned, bool dir, const U8Shape &s, int grid, hipStream_t stream);
+                             bool aligned, bool dir, const U8Shape &s, int grid, hipStream_t stream,
+                             uint32_t *claims = nullptr);
 
 // Wave-tiles of image `img` (tiled by u8_tile with th rows per tile): the
 // complete four-tile strips side by side (kind 0) in tall row chunks

@@ -423,11 +423,11 @@ int plan_setup(sobel4x5_plan_s *p, const U8Shape &shape)
     return ok();
 }
 
-int plan_direct_launch(sobel4x5_plan_s *p, hipStream_t st)
+int plan_direct_launch(sobel4x5_plan_s *p, hipStream_t st, uint32_t *claims = nullptr)
 {
     uint32_t *queue = p->shape.waves == kStaticGrid ? nullptr : p->d_queue;
     hipError_t e = launch_u8_batched(p->d_jobs, p->d_tiles, p->total, queue, p->border, p->aligned, p->dir,
-                                     p->shape, p->grid, st);
+                                     p->shape, p->grid, st, claims);
     return e == hipSuccess ? ok() : hip_fail(e, "batched launch");
 }
 
@@ -962,6 +962,21 @@ int sobel4x5_plan_launch(sobel4x5_plan plan, void *stream)
         return e == hipSuccess ? ok() : hip_fail(e, "hipGraphLaunch");
     }
     return plan_direct_launch(plan, st);
+}
+
+int sobel4x5_debug_plan_claims(sobel4x5_plan plan, uint32_t *claims, int64_t capacity, int64_t *ntiles, void *stream)
+{
+    if (!plan || plan->magic != kPlanMagic) return fail(SOBEL4X5_EINVAL, "invalid plan handle");
+    if (!ntiles) return fail(SOBEL4X5_EINVAL, "ntiles is NULL");
+    *ntiles = plan->total;
+    if (!claims) return ok();
+    if (capacity < plan->total)
+        return fail(SOBEL4X5_EINVAL, "claims holds %lld counters, the plan has %d tiles", (long long)capacity,
+                    plan->total);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = guard(hipMemsetAsync(claims, 0, sizeof(uint32_t) * (size_t)std::max<int32_t>(plan->total, 1), st));
+    if (e != hipSuccess) return hip_fail(e, "clearing the claim counters");
+    return plan_direct_launch(plan, st, claims);
 }
 
 int sobel4x5_plan_info(sobel4x5_plan plan, int32_t *px_per_lane, int32_t *rows_per_tile, int32_t *waves_per_group,

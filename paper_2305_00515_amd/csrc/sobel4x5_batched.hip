@@ -48,6 +48,9 @@ __device__ __forceinline__ Sweep batch_geometry(const U8Job &J, const int4 &ti, 
 // queue[1]; the last wave out resets both words for the next launch.  With
 // queue == nullptr the grid holds one wave per tile instead (static form).  A
 // ticket indexes the host-built tile table, so finding a tile is one load.
+// claims (debug launches only, else nullptr): one counter per tile, plus one
+// for every time a wave takes that tile, so a launch that leaves any counter
+// other than 1 has skipped or repeated a tile.
 // DIR: images whose job asks for them also get their directional planes.
 // The sweeps here cover short row ranges (tiles of a few tens of rows) and
 // use the loop that leaves after any step: measured 2% faster here than
@@ -56,7 +59,7 @@ template <int PPL, int OFF, bool ALIGNED, bool DIR, int BM>
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
     single_waves(PPL, kOp4x5, ALIGNED, DIR), single_waves(PPL, kOp4x5, ALIGNED, DIR)))) void k_u8_batched(const U8Job *__restrict__ jobs,
                                                             const int4 *__restrict__ tiles, int32_t total,
-                                                            uint32_t *queue, int TH)
+                                                            uint32_t *queue, int TH, uint32_t *claims)
 {
     constexpr int TW = 16 * PPL;
     constexpr int WV = single_waves(PPL, kOp4x5, ALIGNED, DIR);
@@ -98,6 +101,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
         // binomial kernel copies its table while the tile's first rows load
         // (every wave of the workgroup reaches that one barrier)
         const int t = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        if (claims != nullptr && lane == 0 && t < total) atomicAdd(&claims[t], 1u);
         if constexpr (BIN) {
             if (t < total)
                 run_tile(t, LutPrelude<64 * kWaves>{{}, lut});
@@ -115,6 +119,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(
         if (lane == 0) tv = atomicAdd(&queue[0], 1u);
         const int t = __builtin_amdgcn_readfirstlane((int)tv);
         if (t >= total) break;
+        if (claims != nullptr && lane == 0) atomicAdd(&claims[t], 1u);
         run_tile(t, NoPrelude{});
     }
     if (lane == 0) {
@@ -174,11 +179,11 @@ void batched_tiles(const U8Job &j, int32_t img, int th, std::vector<int4> &first
 }
 
 hipError_t launch_u8_batched(const U8Job *jobs, const int4 *tiles, int32_t total, uint32_t *queue, int border,
-                             bool aligned, bool dir, const U8Shape &s, int grid, hipStream_t st)
+                             bool aligned, bool dir, const U8Shape &s, int grid, hipStream_t st, uint32_t *claims)
 {
     const void *fn = pick_batched(s.ppl, border, aligned, dir);
     int th = s.th;
-    void *args[] = {(void *)&jobs, (void *)&tiles, (void *)&total, (void *)&queue, (void *)&th};
+    void *args[] = {(void *)&jobs, (void *)&tiles, (void *)&total, (void *)&queue, (void *)&th, (void *)&claims};
     return hipLaunchKernel(fn, dim3(grid), dim3(64 * kWaves), args, 0, st);
 }
 

@@ -156,6 +156,10 @@ static void check_batch(void)
     memset(bogus, 0x11, sizeof bogus);
     EXPECT(sobel4x5_plan_destroy((sobel4x5_plan)(void *)bogus), SOBEL4X5_EINVAL);
     EXPECT(sobel4x5_plan_info(NULL, NULL, NULL, NULL, NULL), SOBEL4X5_EINVAL);
+    {
+        int64_t nt = -1;
+        EXPECT(sobel4x5_debug_plan_claims(NULL, NULL, 0, &nt, NULL), SOBEL4X5_EINVAL);
+    }
 }
 
 static void check_f32(void)

@@ -15,7 +15,7 @@ hipError_t launch_u8_mfma(const U8Job &, int, int, hipStream_t) { return hipErro
 hipError_t launch_u8_2dir(const U8Job &, int, int, const U8Shape &, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_u8_2dir_zr(const U8Job &, int, int, const U8Shape &, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_u8_batched(const U8Job *, const int4 *, int32_t, uint32_t *, int, bool, bool, const U8Shape &, int,
-                             hipStream_t)
+                             hipStream_t, uint32_t *)
 {
     return hipErrorNoDevice;
 }

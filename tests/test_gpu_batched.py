@@ -165,3 +165,28 @@ def test_one_shot_calls_on_two_streams(oracle_mod, sobel_lib, gpu):
         sobel_lib.sobel4x5_batched(srcs, mags)
     torch.cuda.synchronize()
     check_all(oracle_mod, imgs, mags)
+
+
+@pytest.mark.parametrize("static", ["0", "1"])
+@pytest.mark.parametrize("planes", [False, True])
+def test_every_tile_taken_once(oracle_mod, sobel_lib, gpu, monkeypatch, static, planes):
+    """Work-queue check (sobel4x5_debug_plan_claims): in both grid forms every
+    tile of the plan's table is taken by exactly one wave, on three claim
+    launches interleaved with graph launches of the same plan (the persistent
+    queue resets itself between launches); the outputs stay exact."""
+    monkeypatch.setenv("SOBEL4X5_BATCH_STATIC", static)
+    sizes = SMALL + [(2048, 3000), (1500, 517)]
+    imgs, srcs, mags = make_batch(sizes, gpu, seed0=4000)
+    dirs = ([[torch.zeros(m.shape, dtype=torch.int16, device=gpu) for _ in range(4)] for m in imgs]
+            if planes else None)
+    plan = sobel_lib.Plan(srcs, mags, dir_type=1, dirs=dirs) if planes else sobel_lib.Plan(srcs, mags)
+    for rep in range(3):
+        c = plan.claims()
+        torch.cuda.synchronize()
+        counts = c.cpu().numpy()
+        assert counts.size > 0
+        assert (counts == 1).all(), "rep %d: %d tiles skipped, %d taken more than once" % (
+            rep, int((counts == 0).sum()), int((counts > 1).sum()))
+        plan.launch()
+    check_all(oracle_mod, imgs, mags)
+    plan.close()
