@@ -60,6 +60,12 @@ hipError_t launch_u8_single_zr(const U8Job &j, int border, const U8Shape &s, hip
 // rounds of resident waves).  `border`: the public code.
 hipError_t launch_u8_mfma(const U8Job &j, int border, int waves, hipStream_t stream);
 
+// Magnitudes of four run-time kernels (HOST array of 4*25 int32, the layout
+// of sobel4x5_u8_weighted, already validated) on the matrix cores, when
+// every weight fits int8 (mfma_weights_fit).
+bool mfma_weights_fit(const int32_t *weights);
+hipError_t launch_u8_mfma_weighted(const U8Job &j, int border, const int32_t *weights, int waves, hipStream_t stream);
+
 // Two-directional operators on the single-image sweep: op 1 = the 0 / 90 deg
 // filters of the 5x5 operator, op 2 = the 3x3 pair (VALID: off = 1).  The
 // job's Wo, Ho and tiling are those of the operator's own border rule.

@@ -1240,6 +1240,16 @@ int sobel4x5_u8_weighted(const uint8_t *src, int32_t width, int32_t height, int6
     int32_t Wo, Ho;
     if (int rc = validate_u8(src, width, height, src_pitch, border, out, &Wo, &Ho)) return rc;
     if (int rc = sobel4x5_validate_weights(weights, out->dir_type)) return rc;
+    // magnitudes alone with weights that fit int8 (the family K(a, b, n, m)
+    // with small weights, Eq. (sobel5_1) among them): the matrix-core form
+    if (out->dir_type == SOBEL4X5_DIR_NONE && out->mag && env_int("SOBEL4X5_W_MFMA", 1) == 1 &&
+        mfma_weights_fit(weights)) {
+        const U8Job mj = make_job(src, width, height, src_pitch, Wo, Ho, out->mag, out->mag_pitch, nullptr, 0,
+                                  SOBEL4X5_DIR_NONE);
+        hipError_t e = guard(launch_u8_mfma_weighted(mj, border, weights, env_int("SOBEL4X5_U8_WAVES", 0),
+                                                     static_cast<hipStream_t>(stream)));
+        return e == hipSuccess ? ok() : hip_fail(e, "sobel4x5_u8_weighted launch");
+    }
     WJob j{};
     j.src = src;
     j.mag = out->mag;

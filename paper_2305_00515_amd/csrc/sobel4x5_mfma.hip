@@ -28,7 +28,28 @@ __global__ __launch_bounds__(64 * kMWaves) __attribute__((amdgpu_waves_per_eu(4,
     const int sx = w % ntx, ch = w / ntx;
     const int b0 = (int)((int64_t)ch * nty / nchunk), b1 = (int)((int64_t)(ch + 1) * nty / nchunk);
     const u32 tile = (u32)(size_t)(LDS uint8_t *)lds + (u32)(kLutTSize + (wv & (kMWaves - 1)) * kMTileBytes);
-    mfma_strip<OFF, BM>(J, sx, b0, b1, tile, (const LDS uint8_t *)lds);
+    v4i A[3];
+    mfma_a_default(A);
+    mfma_strip<OFF, BM>(J, sx, b0, b1, tile, A, MagT{(const LDS uint8_t *)lds});
+}
+
+// Run-time kernels (weights fitting int8): the same sweep, weight operands
+// from the launch's arguments, no table (square-root rounding).
+template <int OFF, int BM, bool CLAMP>
+__global__ __launch_bounds__(64 * kMWaves) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_u8_mfma_w(U8Job J, int nchunk,
+                                                                                                     MfmaWeights W)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kMWaves * kMTileBytes];
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int ntx = (J.Wo + kMCols - 1) / kMCols, nty = (J.Ho + kMRows - 1) / kMRows;
+    const int w = (int)blockIdx.x * kMWaves + wv;
+    if (w >= ntx * nchunk) return;
+    const int sx = w % ntx, ch = w / ntx;
+    const int b0 = (int)((int64_t)ch * nty / nchunk), b1 = (int)((int64_t)(ch + 1) * nty / nchunk);
+    const u32 tile = (u32)(size_t)(LDS uint8_t *)lds + (u32)((wv & (kMWaves - 1)) * kMTileBytes);
+    v4i A[3];
+    mfma_a_runtime(W, A);
+    mfma_strip<OFF, BM>(J, sx, b0, b1, tile, A, MagS<CLAMP>{});
 }
 
 const void *mfma_fn(int border)
@@ -38,6 +59,17 @@ const void *mfma_fn(int border)
     case 2: return reinterpret_cast<const void *>(&k_u8_mfma<0, kBmZero>);
     case 3: return reinterpret_cast<const void *>(&k_u8_mfma<0, kBmRefl>);
     default: return reinterpret_cast<const void *>(&k_u8_mfma<0, kBmRep>);
+    }
+}
+
+template <bool CLAMP>
+const void *mfma_w_fn(int border)
+{
+    switch (border) {
+    case 1: return reinterpret_cast<const void *>(&k_u8_mfma_w<2, kBmRep, CLAMP>);
+    case 2: return reinterpret_cast<const void *>(&k_u8_mfma_w<0, kBmZero, CLAMP>);
+    case 3: return reinterpret_cast<const void *>(&k_u8_mfma_w<0, kBmRefl, CLAMP>);
+    default: return reinterpret_cast<const void *>(&k_u8_mfma_w<0, kBmRep, CLAMP>);
     }
 }
 
@@ -54,10 +86,12 @@ int mfma_slots(const void *fn)
 
 }  // namespace
 
-hipError_t launch_u8_mfma(const U8Job &j, int border, int waves, hipStream_t st)
+namespace {
+
+// Waves of a launch over the image's 32 x 128 tiles: `waves` (> 0) or four
+// rounds of resident waves, as runs of whole tiles per strip.
+hipError_t mfma_launch(const void *fn, const U8Job &j, int waves, void *extra, hipStream_t st)
 {
-    if (j.Wo <= 0 || j.Ho <= 0) return hipSuccess;
-    const void *fn = mfma_fn(border);
     const int64_t ntx = (j.Wo + kMCols - 1) / kMCols, nty = (j.Ho + kMRows - 1) / kMRows;
     // default: four rounds of resident waves, about one tile each (8192^2:
     // 56.1 us against 62.5 for one round of four tiles per wave)
@@ -69,8 +103,42 @@ hipError_t launch_u8_mfma(const U8Job &j, int border, int waves, hipStream_t st)
     const int grid = (int)((total + kMWaves - 1) / kMWaves);
     U8Job jj = j;
     int nc = (int)nchunk;
-    void *args[] = {(void *)&jj, (void *)&nc};
+    void *args[] = {(void *)&jj, (void *)&nc, extra};
     return hipLaunchKernel(fn, dim3(grid), dim3(64 * kMWaves), args, 0, st);
+}
+
+}  // namespace
+
+hipError_t launch_u8_mfma(const U8Job &j, int border, int waves, hipStream_t st)
+{
+    if (j.Wo <= 0 || j.Ho <= 0) return hipSuccess;
+    return mfma_launch(mfma_fn(border), j, waves, nullptr, st);
+}
+
+bool mfma_weights_fit(const int32_t *weights)
+{
+    for (int i = 0; i < 100; ++i)
+        if (weights[i] < -128 || weights[i] > 127) return false;
+    return true;
+}
+
+hipError_t launch_u8_mfma_weighted(const U8Job &j, int border, const int32_t *weights, int waves, hipStream_t st)
+{
+    if (j.Wo <= 0 || j.Ho <= 0) return hipSuccess;
+    struct Taps {
+        const int32_t *w;
+        int operator()(int f, int dy, int dx) const { return w[25 * f + 5 * dy + dx]; }
+    };
+    MfmaWeights W = mfma_weights(Taps{weights});
+    // without the clamp, 4 G^2 must stay below 2^31: |G| <= 128 sum|k| <= 23168
+    int64_t most = 0;
+    for (int f = 0; f < 4; ++f) {
+        int64_t a = 0;
+        for (int t = 0; t < 25; ++t) a += weights[25 * f + t] < 0 ? -(int64_t)weights[25 * f + t] : weights[25 * f + t];
+        most = std::max(most, a);
+    }
+    const void *fn = most <= 181 ? mfma_w_fn<false>(border) : mfma_w_fn<true>(border);
+    return mfma_launch(fn, j, waves, (void *)&W, st);
 }
 
 }  // namespace s4x5

@@ -24,6 +24,10 @@
 // multiply(-add).  The magnitude round(sqrt(S)), capped at 255, is read from
 // the table of T (kMagLutT, T >= 32386 reads 255) at min(T, 32767).
 //
+// The same products serve run-time kernels whose weights fit int8 (the
+// family of Eq. (sobel5_param) with small weights), with S = sum G^2 and a
+// square root for the rounding (MagS).
+//
 // A lane of D holds, for its output row n = lane % 32 and half
 // h = lane / 32, the four responses of columns 4h .. 4h + 3 of the group:
 // its four magnitude bytes are one contiguous dword of the output row.
@@ -100,13 +104,17 @@ static_assert(16 * kMPieces == kMInLead + kMCols + 4, "input row = lead + output
 static_assert(kMPitch % 8 == 0 && kMPitch >= 16 * kMPieces, "row pitch");
 static_assert(kLutTSize + kMWaves * kMTileBytes <= 81920, "two workgroups per CU");
 
-// Weight operand of product t for every lane: 16 bytes, k = 16 (lane / 32) + byte.
-struct AWords {
+// Weight operands of the three products for every lane: 16 bytes each,
+// k = 16 (lane / 32) + byte, from four 5x5 kernels k[f][dy][dx] whose
+// weights fit int8 (used at compile time for the operator of Eq. (sobel5_1)
+// and on the host for run-time kernels).
+struct MfmaWeights {
     u32 w[3][64][4];
 };
-constexpr AWords make_awords()
+template <class K>
+constexpr MfmaWeights mfma_weights(const K &k)
 {
-    AWords a{};
+    MfmaWeights a{};
     for (int t = 0; t < 3; ++t)
         for (int lane = 0; lane < 64; ++lane) {
             const int m = lane & 31, g = lane >> 5;
@@ -114,13 +122,35 @@ constexpr AWords make_awords()
             const int dy = 2 * t + g;
             for (int b = 0; b < 16; ++b) {
                 const int dx = b - 2 - s;
-                const int v = (dy <= 4 && dx >= 0 && dx <= 4) ? kResp5.k[f][dy][dx] : 0;
+                const int v = (dy <= 4 && dx >= 0 && dx <= 4) ? k(f, dy, dx) : 0;
                 a.w[t][lane][b >> 2] |= (u32)(uint8_t)(int8_t)v << (8 * (b & 3));
             }
         }
     return a;
 }
-constexpr AWords kAWords = make_awords();
+struct Resp5Taps {
+    constexpr int operator()(int f, int dy, int dx) const { return kResp5.k[f][dy][dx]; }
+};
+constexpr MfmaWeights kAWords = mfma_weights(Resp5Taps{});
+
+// The lane's three weight operands: of the operator of Eq. (sobel5_1) from
+// the table above, or run-time ones (built on the host by mfma_weights).
+__device__ __forceinline__ void mfma_a_default(v4i (&A)[3])
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+        A[t] = v4i{(int)kAWords.w[t][lane][0], (int)kAWords.w[t][lane][1], (int)kAWords.w[t][lane][2],
+                   (int)kAWords.w[t][lane][3]};
+}
+
+__device__ __forceinline__ void mfma_a_runtime(const MfmaWeights &W, v4i (&A)[3])
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+        A[t] = v4i{(int)W.w[t][lane][0], (int)W.w[t][lane][1], (int)W.w[t][lane][2], (int)W.w[t][lane][3]};
+}
 
 // Index of input position i of an axis of n pixels under border rule BM
 // (kBmZero: -1 for a position outside).
@@ -279,24 +309,59 @@ __device__ __forceinline__ void mfma_commit(const MfmaFetch &f, u32 tile)
     }
 }
 
-// Output bytes of one group after the table reads: one dword of the lane.
-__device__ __forceinline__ u32 mfma_pack(const u32 (&mb)[4])
-{
-    return lshl_or(lshl_or(mb[3], 8, mb[2]), 16, lshl_or(mb[1], 8, mb[0]));
-}
-
-// Table indices of the lane's four pixels of one group; their table reads.
-__device__ __forceinline__ void mfma_lookup(const v16i &D, const LDS uint8_t *lut, u32 (&mb)[4])
-{
+// Magnitude policies: lookup() turns a group's responses (D: four pixels of
+// the lane, four responses each) into what pack() makes the lane's output
+// dword of, one pipeline step later.
+//
+// MagT, the operator of Eq. (sobel5_1): the responses are E1, E2, Hp, Hm;
+// T = E1^2 + E2^2 + Hp^2 + Hm^2 indexes the T table in LDS (reads issued
+// in lookup, consumed in pack).
+struct MagT {
+    const LDS uint8_t *lut;
+    __device__ __forceinline__ void lookup(const v16i &D, u32 (&mb)[4]) const
+    {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        int T = __mul24(D[4 * i], D[4 * i]);
-        T = sq24_acc(D[4 * i + 1], T);
-        T = sq24_acc(D[4 * i + 2], T);
-        T = sq24_acc(D[4 * i + 3], T);
-        mb[i] = lut[min((u32)T, (u32)kLutTSize - 1u)];
+        for (int i = 0; i < 4; ++i) {
+            int T = __mul24(D[4 * i], D[4 * i]);
+            T = sq24_acc(D[4 * i + 1], T);
+            T = sq24_acc(D[4 * i + 2], T);
+            T = sq24_acc(D[4 * i + 3], T);
+            mb[i] = lut[min((u32)T, (u32)kLutTSize - 1u)];
+        }
     }
-}
+    __device__ __forceinline__ u32 pack(const u32 (&mb)[4]) const
+    {
+        return lshl_or(lshl_or(mb[3], 8, mb[2]), 16, lshl_or(mb[1], 8, mb[0]));
+    }
+};
+
+// MagS, four run-time kernels G_f (Eq. (sobel5_param) or any half-turn
+// antisymmetric ones): S = sum G_f^2, min(255, round(sqrt(S))).  CLAMP:
+// each G is first clamped to [-256, 256] (one G of 256 or more already
+// makes S >= 65536, which rounds to 255, and the clamped S stays below
+// 2^19); without it the kernels' absolute sums must keep 4 G^2 < 2^31.
+// (float)S is exact below 2^24 and monotone above, where the result
+// saturates; v_sqrt_f32 is within 1 ulp and round(sqrt(S)) is never a tie,
+// with a margin that 1 ulp does not cross; v_cvt_pk_u8_f32 rounds to
+// nearest and saturates to [0, 255].
+template <bool CLAMP>
+struct MagS {
+    __device__ __forceinline__ static int g(int v) { return CLAMP ? min(max(v, -256), 256) : v; }
+    __device__ __forceinline__ void lookup(const v16i &D, u32 (&mb)[4]) const
+    {
+        u32 out = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int S = __mul24(g(D[4 * i]), g(D[4 * i]));
+            S = sq24_acc(g(D[4 * i + 1]), S);
+            S = sq24_acc(g(D[4 * i + 2]), S);
+            S = sq24_acc(g(D[4 * i + 3]), S);
+            out = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_amdgcn_sqrtf((float)S), i, out);
+        }
+        mb[0] = out;
+    }
+    __device__ __forceinline__ u32 pack(const u32 (&mb)[4]) const { return mb[0]; }
+};
 
 // The 32 x 128 output tile at (y0, X) from the wave's LDS tile (byte address
 // `tile`).  FULL: every output of the tile lies inside the image.  Pipeline
@@ -311,9 +376,8 @@ __device__ __forceinline__ void mfma_lookup(const v16i &D, const LDS uint8_t *lu
 // lane (n, 0) holds columns 8j .. 8j + 15 and lane (n, 1) 8j + 16 ..
 // 8j + 31: one 16-byte store each, instead of four 4-byte stores that
 // would reach L2 as 8-byte pieces of 32 rows.
-template <bool FULL>
-__device__ __forceinline__ void mfma_tile(const U8Job &J, int y0, int X, u32 tile, const v4i (&A)[3],
-                                          const LDS uint8_t *lut)
+template <bool FULL, class Mag>
+__device__ __forceinline__ void mfma_tile(const U8Job &J, int y0, int X, u32 tile, const v4i (&A)[3], const Mag &mag)
 {
     // a fresh base each tile, so that the 48 operand addresses of the tile
     // are the three row bases plus immediate offsets, not registers held
@@ -356,32 +420,28 @@ __device__ __forceinline__ void mfma_tile(const U8Job &J, int y0, int X, u32 til
         if (j + 1 < kMGroups) Dn = mfma_products(A, B);
         if (j + 2 < kMGroups) mfma_load_b(rb, j + 2, B);
         u32 mb[4];
-        mfma_lookup(D, lut, mb);
+        mag.lookup(D, mb);
         if (j > 0) {
-            out[(j - 1) & 3] = mfma_pack(mbp);
+            out[(j - 1) & 3] = mag.pack(mbp);
             if (((j - 1) & 3) == 3) store4(out, j - 4);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) mbp[i] = mb[i];
         __builtin_amdgcn_sched_barrier(0);
     }
-    out[3] = mfma_pack(mbp);
+    out[3] = mag.pack(mbp);
     store4(out, kMGroups - 4);
 }
 
 // One wave: tiles [b0, b1) of column strip sx, top to bottom, in the LDS
-// tile at byte address `tile`.  An interior tile's rows are fetched into
-// registers while the tile before it is computed, then written to LDS;
-// the tiles at the image edges load through the border rule in between.
-template <int OFF, int BM>
-__device__ __forceinline__ void mfma_strip(const U8Job &J, int sx, int b0, int b1, u32 tile, const LDS uint8_t *lut)
+// tile at byte address `tile`, with weight operands A.  An interior tile's
+// rows are fetched into registers while the tile before it is computed,
+// then written to LDS; the tiles at the image edges load through the border
+// rule in between.
+template <int OFF, int BM, class Mag>
+__device__ __forceinline__ void mfma_strip(const U8Job &J, int sx, int b0, int b1, u32 tile, const v4i (&A)[3],
+                                           const Mag &mag)
 {
-    const int lane = threadIdx.x & 63;
-    v4i A[3];
-#pragma unroll
-    for (int t = 0; t < 3; ++t)
-        A[t] = v4i{(int)kAWords.w[t][lane][0], (int)kAWords.w[t][lane][1], (int)kAWords.w[t][lane][2],
-                   (int)kAWords.w[t][lane][3]};
     const int X = sx * kMCols;
     const bool cols_full = X + kMCols <= J.Wo;
     LDS uint8_t *tp = (LDS uint8_t *)(size_t)tile;
@@ -402,9 +462,9 @@ __device__ __forceinline__ void mfma_strip(const U8Job &J, int sx, int b0, int b
         // the tile's rows were written by other lanes of this wave
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         if (cols_full && y0 + kMRows <= J.Ho)
-            mfma_tile<true>(J, y0, X, tile, A, lut);
+            mfma_tile<true>(J, y0, X, tile, A, mag);
         else
-            mfma_tile<false>(J, y0, X, tile, A, lut);
+            mfma_tile<false>(J, y0, X, tile, A, mag);
         // every operand read of this tile has returned (the products and
         // stores consumed them) before its rows are overwritten
         if (fetch_next)

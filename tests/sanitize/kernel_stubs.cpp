@@ -12,6 +12,8 @@ void u8_tile(U8Job &, const U8Shape &) {}
 hipError_t launch_u8_single(const U8Job &, int, const U8Shape &, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_u8_single_zr(const U8Job &, int, const U8Shape &, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_u8_mfma(const U8Job &, int, int, hipStream_t) { return hipErrorNoDevice; }
+bool mfma_weights_fit(const int32_t *) { return false; }
+hipError_t launch_u8_mfma_weighted(const U8Job &, int, const int32_t *, int, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_u8_2dir(const U8Job &, int, int, const U8Shape &, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_u8_2dir_zr(const U8Job &, int, int, const U8Shape &, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_u8_batched(const U8Job *, const int4 *, int32_t, uint32_t *, int, bool, bool, const U8Shape &, int,

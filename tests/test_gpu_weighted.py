@@ -105,3 +105,36 @@ def test_weighted_rejects_bad_weights(sobel_lib, gpu):
     big = sobel_lib.family_weights(*sobel_lib.family_products(1, 3, 5, 10))
     with pytest.raises(sobel_lib.SobelError):
         sobel_lib.sobel4x5_u8_weighted(src, big, dir_type=sobel_lib.DIR_S16)
+
+
+# Magnitudes alone with weights that fit int8 take the matrix-core form
+# (SOBEL4X5_W_MFMA=0 forces the kernel above): both paths, unclamped
+# (sum |k| <= 181 per kernel) and clamped sums, every border rule.
+@pytest.mark.parametrize("path", ["1", "0"])
+@pytest.mark.parametrize("amp", [1, 3, 20, 63])
+def test_magnitude_only_both_paths(oracle_mod, sobel_lib, gpu, monkeypatch, path, amp):
+    monkeypatch.setenv("SOBEL4X5_W_MFMA", path)
+    rng = np.random.default_rng(100 + amp)
+    w = antisym_random(rng, amp)
+    assert np.abs(w).max() <= 127
+    for (h, wd) in [(1, 1), (5, 5), (33, 129), (97, 301), (64, 1030), (40, 4099)]:
+        img = synth.rect_image(h, wd, h * 17 + wd + amp)
+        low = (img % 4).astype(np.uint8)
+        for im in (img, low):
+            for border in (0, 1, 2, 3):
+                if border == 1 and (h < 5 or wd < 5):
+                    continue
+                mag, _ = run(sobel_lib, im, gpu, w, border, 0)
+                om, _ = oracle_mod.sobel_u8(im, border, weights=w, want_dir=False)
+                assert np.array_equal(mag, om), (amp, h, wd, border, int((mag != om).sum()))
+
+
+@pytest.mark.parametrize("abnm", FAMILIES)
+def test_family_magnitudes_full_size(oracle_mod, sobel_lib, gpu, abnm):
+    """The family's magnitudes at 4096^2 (the matrix-core form whenever the
+    weights fit int8), every pixel against the oracle."""
+    w = sobel_lib.family_weights(*sobel_lib.family_products(*abnm))
+    img = synth.rect_image(4096, 4096, 9)
+    mag, _ = run(sobel_lib, img, gpu, w, 0, 0)
+    om, _ = oracle_mod.sobel_u8(img, 0, weights=w, want_dir=False)
+    assert np.array_equal(mag, om), int((mag != om).sum())
