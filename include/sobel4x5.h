@@ -159,7 +159,9 @@ int sobel4x5_validate_u8_op(const uint8_t *src, int32_t width, int32_t height, i
  *   Anything else is SOBEL4X5_EINVAL.  Other arguments, outputs and the
  *   uint8 rounding min(255, round(sqrt(S))) are as for sobel4x5_u8.  The
  *   default weights of Eq. (sobel5_1) give the same results as sobel4x5_u8,
- *   which runs them on a faster path.
+ *   which runs them on a faster path.  Magnitude-only calls whose weights
+ *   all lie in [-128, 127] run on the matrix cores (same results; the
+ *   environment variable SOBEL4X5_W_MFMA=0 selects the vector kernel).
  */
 int sobel4x5_u8_weighted(const uint8_t *src, int32_t width, int32_t height, int64_t src_pitch,
                          int32_t border, const int32_t *weights, const sobel4x5_outputs *out,
