@@ -223,12 +223,18 @@ U8Shape default_shape(int32_t Wo, int32_t Ho, int32_t dir_type, int32_t op = SOB
     // (graph replay: 512^2 3.48 against 4.32 us, 1920x1080 6.92 against
     // 9.33, 3840x2160 12.6 against 13.9; from 4096^2 on the binomial form
     // wins: 17.4 against 18.1), with 4-row minimum ranges from 2048 rows on.
-    if (op == SOBEL4X5_OP_4DIR_5X5 && dir_type == SOBEL4X5_DIR_NONE) {
+    // The same holds for the 0 / 90 deg pair of the 5x5 operator at 8 pixels
+    // per lane (graph replay: 1024^2 4.00 against 4.34 us; 8192^2 binomial
+    // 31.2 against 37.2); at 16 (from 2048^2 on) its separable kernel that
+    // can also write planes runs one wave per SIMD fewer, and the binomial
+    // form stays (2048^2: 6.96 against 7.39 us).
+    if ((op == SOBEL4X5_OP_4DIR_5X5 || (op == SOBEL4X5_OP_2DIR_5X5 && s.ppl == 8)) &&
+        dir_type == SOBEL4X5_DIR_NONE) {
         const int64_t strips8 = (Wo + 511) / 512;
         const int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(12 * (int64_t)device_cus() / strips8, Ho / 2));
         if (Ho < 8 * nchunk) {
             s.sep = true;
-            if (Ho >= 2048) s.min_rows = 4;
+            if (op == SOBEL4X5_OP_4DIR_5X5 && Ho >= 2048) s.min_rows = 4;
         }
     }
     const int ppl = env_int("SOBEL4X5_U8_PPL", 0);

@@ -92,9 +92,9 @@ constexpr int kOp4x5 = 0;   // Eq. (sobel5_1) + Eq. (sobel5_2): four directions,
 constexpr int kOp2x5 = 1;   // the 0 and 90 deg filters of Eq. (sobel5_1) alone
 constexpr int kOp2x3 = 2;   // Eq. (sobel3_1) + Eq. (sobel3_2): the 3x3 pair
 
-// Kernels in the binomial form (sweep4): the four-directional operator
-// without directional planes (see sweep).
-constexpr bool binomial_form(int opr, bool dir) { return opr == kOp4x5 && !dir; }
+// Kernels in the binomial form (sweep4): the four-directional operator and
+// its 0 / 90 deg pair, without directional planes (see sweep).
+constexpr bool binomial_form(int opr, bool dir) { return (opr == kOp4x5 || opr == kOp2x5) && !dir; }
 
 // v_perm selector: byte0 <- byte `lob` of the low source, byte2 <- byte
 // `hib` of the high source, bytes 1 and 3 <- 0: two zero-extended pixels.
@@ -416,6 +416,20 @@ __device__ __forceinline__ void row_filters_bin(const v2s (&R)[NP + 4], v2s (&b3
         ch[x] = (b1[x] + b1[x + 3]) * k3 + R[x + 2];
         mh[x] = (b1[x + 1] + R[x + 3]) * k2 + (b3[x] + b3[x + 1]);
     }
+}
+
+// The binomial row sums alone (b3 = (1 + v)^3 p), for the operator without
+// the diagonal pair.
+template <int NP>
+__device__ __forceinline__ void row_sums_bin(const v2s (&R)[NP + 4], v2s (&b3)[NP + 1])
+{
+    v2s b1[NP + 3], b2[NP + 2];
+#pragma unroll
+    for (int k = 0; k < NP + 3; ++k) b1[k] = R[k] + R[k + 1];
+#pragma unroll
+    for (int k = 0; k < NP + 2; ++k) b2[k] = b1[k] + b1[k + 1];
+#pragma unroll
+    for (int k = 0; k < NP + 1; ++k) b3[k] = b2[k] + b2[k + 1];
 }
 
 // Replace the bytes of `v` at positions >= keep (0..4) by `fill` (a byte
@@ -989,8 +1003,10 @@ __device__ __forceinline__ void store_mag_bytes(const U8Job &J, int yo, int xo, 
     }
 }
 
-// Four-directional 5x5 sweep in the binomial form, magnitude only.  With u
-// one row down and v one column right, the 0 and 90 deg filters of
+// 5x5 sweep in the binomial form, magnitude only: the four-directional
+// operator, or (OPR == kOp2x5) its 0 and 90 deg filters alone, for which
+// S = Gx^2 + Gy^2 = 2 (E1^2 + E2^2) and the diagonal terms below are
+// skipped.  With u one row down and v one column right, the 0 and 90 deg filters of
 // Eq. (sobel5_1) share the factor (1 + u)^3 (1 + v)^3:
 //   K_x + K_y = 2 (1 + u)^3 (1 + v)^3 (uv - 1),
 //   K_x - K_y = 2 (1 + u)^3 (1 + v)^3 (v - u),
@@ -1015,11 +1031,13 @@ __device__ __forceinline__ void store_mag_bytes(const U8Job &J, int yo, int xo, 
 // The LDS reads of one row's magnitudes are issued at the end of its step
 // and consumed by the next step's store, so their latency hides behind a
 // whole row of arithmetic.
-template <int PPL, int OFF, bool ALIGNED, bool FAST, bool EDGE, int BM, bool BLOCKS, class Prelude>
+template <int PPL, int OFF, bool ALIGNED, bool FAST, bool EDGE, int BM, bool BLOCKS, int OPR, class Prelude>
 __device__ __forceinline__ void sweep4(const U8Job &J, const Sweep &g, lds_u8 *lut, Prelude &pre)
 {
     static_assert(!EDGE || FAST, "edge fix-ups by mask exist for fast waves only");
+    static_assert(OPR == kOp4x5 || OPR == kOp2x5, "binomial form of the 5x5 operators");
     constexpr int NP = PPL / 2;
+    constexpr bool DIAG = OPR == kOp4x5;   // the diagonal pair Hp, Hm too
     const int lane16 = threadIdx.x & 15;
     const int xo = g.xo, yo0 = g.yo0, nrow = g.nrow, niter = g.niter;
     const int W = J.W;
@@ -1078,7 +1096,10 @@ __device__ __forceinline__ void sweep4(const U8Job &J, const Sweep &g, lds_u8 *l
         v2s R[NP + 4];
         window(t, raw[S], R);
         v2s hs[NP], hr[NP], ch[NP], mh[NP];
-        row_filters_bin<NP>(R, b3r[S], hs, hr, ch, mh);
+        if constexpr (DIAG)
+            row_filters_bin<NP>(R, b3r[S], hs, hr, ch, mh);
+        else
+            row_sums_bin<NP>(R, b3r[S]);
 #pragma unroll
         for (int k = 0; k < NP + 1; ++k) {
             if constexpr (H >= 1) v1r[S1][k] = b3r[S1][k] + b3r[S][k];   // rows t-1, t
@@ -1088,25 +1109,29 @@ __device__ __forceinline__ void sweep4(const U8Job &J, const Sweep &g, lds_u8 *l
         const v2s k3 = kconst<3>(), km5 = kconst<-5>(), k6 = kconst<6>();
 #pragma unroll
         for (int x = 0; x < NP; ++x) {
-            // Hm of output r - 2 + d takes, from row r: 3 hr - 5 hs at d = -2
-            // and +2, 3 hr at d = -1 and +1, hr + 6 hs at d = 0
-            const v2s B = hr[x] * k3;
-            const v2s A = hs[x] * km5 + B;
-            const v2s C = hs[x] * k6 + hr[x];
-            nacc[S][x] = ch[x];
-            hacc[S][x] = A;
-            if constexpr (H >= 1) {
-                nacc[S1][x] = nacc[S1][x] + mh[x];
-                hacc[S1][x] = hacc[S1][x] + B;
-            }
-            if constexpr (H >= 2) hacc[S2][x] = hacc[S2][x] + C;
-            if constexpr (H >= 3) {
-                nacc[S3][x] = nacc[S3][x] - mh[x];
-                hacc[S3][x] = hacc[S3][x] + B;
+            if constexpr (DIAG) {
+                // Hm of output r - 2 + d takes, from row r: 3 hr - 5 hs at d = -2
+                // and +2, 3 hr at d = -1 and +1, hr + 6 hs at d = 0
+                const v2s B = hr[x] * k3;
+                const v2s A = hs[x] * km5 + B;
+                const v2s C = hs[x] * k6 + hr[x];
+                nacc[S][x] = ch[x];
+                hacc[S][x] = A;
+                if constexpr (H >= 1) {
+                    nacc[S1][x] = nacc[S1][x] + mh[x];
+                    hacc[S1][x] = hacc[S1][x] + B;
+                }
+                if constexpr (H >= 2) hacc[S2][x] = hacc[S2][x] + C;
+                if constexpr (H >= 3) {
+                    nacc[S3][x] = nacc[S3][x] - mh[x];
+                    hacc[S3][x] = hacc[S3][x] + B;
+                }
+                if constexpr (H >= 4) {
+                    Hp[x] = ch[x] - nacc[S4][x];
+                    Hm[x] = hacc[S4][x] + A;
+                }
             }
             if constexpr (H >= 4) {
-                Hp[x] = ch[x] - nacc[S4][x];
-                Hm[x] = hacc[S4][x] + A;
                 E1[x] = Pr[S3][x + 1] - Pr[S4][x];
                 E2[x] = Pr[S4][x + 1] - Pr[S3][x];
             }
@@ -1119,8 +1144,10 @@ __device__ __forceinline__ void sweep4(const U8Job &J, const Sweep &g, lds_u8 *l
         for (int j = 0; j < NP; ++j) {
             u32 T = sq_sat(U2(E1[j]));
             T = sq_sat_acc(U2(E2[j]), T);
-            T = sq_sat_acc(U2(Hp[j]), T);
-            T = sq_sat_acc(U2(Hm[j]), T);
+            if constexpr (DIAG) {
+                T = sq_sat_acc(U2(Hp[j]), T);
+                T = sq_sat_acc(U2(Hm[j]), T);
+            }
             mb[j] = lut[T & 0xffffu];
             mb[j + NP] = lut[T >> 16];
         }
@@ -1212,18 +1239,18 @@ __device__ __forceinline__ void sweep4(const U8Job &J, const Sweep &g, lds_u8 *l
     store_mag_bytes<PPL, FAST>(J, yo0 + niter - 1, xo, FAST || niter - 1 < nrow, mb);
 }
 
-// The four-directional operator's magnitude-only kernels take the binomial
-// form: its passes run once per input row, and it rounds on int16.  Kernels
-// that may write directional planes are bound by those stores (9 or 17
-// bytes a pixel) and keep the separable form, whose per-input-row work is
-// lighter (their row ranges are short), as do the two-directional
-// operators.
+// The 5x5 operators' magnitude-only kernels (four directions, or the 0 and
+// 90 deg pair alone) take the binomial form: its passes run once per input
+// row, and it rounds on int16.  Kernels that may write directional planes
+// are bound by those stores (9 or 17 bytes a pixel) and keep the separable
+// form, whose per-input-row work is lighter (their row ranges are short),
+// as does the 3x3 pair.
 template <int PPL, int OFF, bool ALIGNED, bool DIR, bool FAST, bool EDGE, int OPR, int BM, bool LUT, bool BLOCKS = true,
           class Prelude = NoPrelude>
 __device__ __forceinline__ void sweep(const U8Job &J, const Sweep &g, lds_u8 *lut, Prelude &&pre = Prelude{})
 {
     if constexpr (binomial_form(OPR, DIR)) {
-        sweep4<PPL, OFF, ALIGNED, FAST, EDGE, BM, BLOCKS>(J, g, lut, pre);
+        sweep4<PPL, OFF, ALIGNED, FAST, EDGE, BM, BLOCKS, OPR>(J, g, lut, pre);
     } else {
         pre.issue();
         pre.finish();
