@@ -269,9 +269,9 @@ int sobel4x5_validate_batch(const sobel4x5_image *imgs, int32_t count, int32_t b
  * only, the default tile shape and grid form, no autotuning, no graph), but
  * its job table, tile table and queue counters live in a fixed device buffer
  * of the library, one per device, held until the process ends; the call
- * allocates no device memory (its host-side tables are per-thread buffers
- * that keep their capacity).  It copies the tables into that buffer and
- * launches, both on `stream`.
+ * allocates no memory, device or host (it builds the tables in fixed
+ * static host buffers, one call at a time per process, then copies them
+ * into that device buffer and launches, both on `stream`).
  *   imgs/count/border : as for sobel4x5_batched (magnitudes only).
  *   Limits: count <= SOBEL4X5_NOALLOC_MAX_IMAGES and at most
  *   SOBEL4X5_NOALLOC_MAX_TILES wave-tiles (about 150 per 2048x2048 image);

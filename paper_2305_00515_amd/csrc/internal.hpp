@@ -87,9 +87,30 @@ hipError_t launch_u8_batched(const U8Job *jobs, const int4 *tiles, int32_t total
 
 // Wave-tiles of image `img` (tiled by u8_tile with th rows per tile): the
 // complete four-tile strips side by side (kind 0) in tall row chunks
-// (appended to `first`) and short ones (appended to `last`, queued after
-// every tall chunk of the batch), then the remaining tile columns with four
-// row blocks stacked (kind 1, in `first`).
+// (passed to `first`) and short ones (passed to `last`, queued after every
+// tall chunk of the batch), then the remaining tile columns with four row
+// blocks stacked (kind 1, passed to `first`).
+struct BatchSplit {
+    int tallx;    // tall chunks: tallx tile heights
+    int shortq;   // the last 1/shortq of the rows in chunks of one tile height
+};
+BatchSplit batched_split();
+
+template <class First, class Last>
+void batched_tiles_each(const U8Job &j, int32_t img, int th, First &&first, Last &&last)
+{
+    const BatchSplit sp = batched_split();
+    const int strips = j.ntx / 4, tall = sp.tallx * th;
+    const int htall = (j.Ho - j.Ho / sp.shortq) / tall * tall;
+    for (int y = 0; y < htall; y += tall)
+        for (int s = 0; s < strips; ++s) first(make_int4(img, tall << 1, 4 * s, y));
+    for (int y = htall; y < j.Ho; y += th)
+        for (int s = 0; s < strips; ++s) last(make_int4(img, th << 1, 4 * s, y));
+    for (int tx = 4 * strips; tx < j.ntx; ++tx)
+        for (int y = 0; y < j.Ho; y += 4 * th) first(make_int4(img, 1, tx, y));
+}
+
+// The same into two vectors.
 void batched_tiles(const U8Job &j, int32_t img, int th, std::vector<int4> &first, std::vector<int4> &last);
 
 // Allocation-free batched call (sobel4x5_batched_noalloc): the queue

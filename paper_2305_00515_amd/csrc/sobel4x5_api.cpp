@@ -1053,44 +1053,52 @@ int sobel4x5_batched_noalloc(const sobel4x5_image *imgs, int32_t count, int32_t 
     if (count > kNoallocMaxImages)
         return fail(SOBEL4X5_EINVAL, "%d images: the allocation-free call takes at most %d", count,
                     kNoallocMaxImages);
-    // Tables built on the host in per-thread buffers that keep their
-    // capacity, then one copy into the fixed device buffer on `stream`.
+    // Tables built on the host in fixed static buffers (no allocation, host
+    // or device), then copied into the fixed device buffer on `stream`.  The
+    // lock covers the building and both copies: a copy from pageable memory
+    // has read its source when hipMemcpyAsync returns.
+    static std::mutex mu;
+    static unsigned char stage[kNoallocBytes];     // queue words, jobs, tiles: the device layout
+    static int4 tail[kNoallocMaxTiles];            // short chunks, queued after every other tile
+    std::lock_guard<std::mutex> lk(mu);
     const std::vector<sobel4x5_image> none;
     const U8Shape shape = batch_default_shape(none, false);
-    thread_local std::vector<int4> tiles, tail;
-    thread_local std::vector<unsigned char> stage;
-    tiles.clear();
-    tail.clear();
-    if (stage.size() < kNoallocTilesOff) stage.resize(kNoallocTilesOff);
-    std::memset(stage.data(), 0, kNoallocJobsOff);   // queue words start at zero
+    std::memset(stage, 0, kNoallocJobsOff);   // queue words start at zero
+    int4 *first = reinterpret_cast<int4 *>(stage + kNoallocTilesOff);
+    int32_t nfirst = 0, ntail = 0;
+    bool over = false;
     bool aligned = true;
-    for (int32_t i = 0; i < count; ++i) {
+    for (int32_t i = 0; i < count && !over; ++i) {
         const sobel4x5_image &m = imgs[i];
         int32_t Wo, Ho;
         out_dims(m.width, m.height, border, &Wo, &Ho);
         U8Job j = make_job(m.src, m.width, m.height, m.src_pitch, Wo, Ho, m.mag, m.mag_pitch, nullptr, 0, 0);
         u8_tile(j, shape);
         aligned = aligned && u8_rows_aligned(j) && !(border == SOBEL4X5_BORDER_REFLECT101 && m.width < 3);
-        std::memcpy(stage.data() + kNoallocJobsOff + sizeof(U8Job) * i, &j, sizeof(U8Job));
-        batched_tiles(j, i, shape.th, tiles, tail);
-        if (tiles.size() + tail.size() > (size_t)kNoallocMaxTiles)
-            return fail(SOBEL4X5_EINVAL, "the batch needs more than %d wave-tiles, the allocation-free call's limit",
-                        kNoallocMaxTiles);
+        std::memcpy(stage + kNoallocJobsOff + sizeof(U8Job) * i, &j, sizeof(U8Job));
+        batched_tiles_each(
+            j, i, shape.th,
+            [&](int4 t) {
+                if (nfirst + ntail < kNoallocMaxTiles) first[nfirst++] = t; else over = true;
+            },
+            [&](int4 t) {
+                if (nfirst + ntail < kNoallocMaxTiles) tail[ntail++] = t; else over = true;
+            });
     }
-    const int32_t total = (int32_t)(tiles.size() + tail.size());
-    const size_t bytes = kNoallocTilesOff + sizeof(int4) * total;
-    if (stage.size() < bytes) stage.resize(bytes);
-    std::memcpy(stage.data() + kNoallocTilesOff, tiles.data(), sizeof(int4) * tiles.size());
-    std::memcpy(stage.data() + kNoallocTilesOff + sizeof(int4) * tiles.size(), tail.data(), sizeof(int4) * tail.size());
+    if (over)
+        return fail(SOBEL4X5_EINVAL, "the batch needs more than %d wave-tiles, the allocation-free call's limit",
+                    kNoallocMaxTiles);
+    const int32_t total = nfirst + ntail;
+    std::memcpy(first + nfirst, tail, sizeof(int4) * ntail);
     void *scr = nullptr;
     hipError_t e = guard(noalloc_scratch(&scr));
     if (e != hipSuccess) return hip_fail(e, "looking up the fixed device buffer");
     unsigned char *base = static_cast<unsigned char *>(scr);
     hipStream_t st = static_cast<hipStream_t>(stream);
     // queue words and the count jobs, then the total tiles
-    if ((e = guard(hipMemcpyAsync(base, stage.data(), kNoallocJobsOff + sizeof(U8Job) * count, hipMemcpyHostToDevice,
+    if ((e = guard(hipMemcpyAsync(base, stage, kNoallocJobsOff + sizeof(U8Job) * count, hipMemcpyHostToDevice,
                                   st))) != hipSuccess ||
-        (e = guard(hipMemcpyAsync(base + kNoallocTilesOff, stage.data() + kNoallocTilesOff, sizeof(int4) * total,
+        (e = guard(hipMemcpyAsync(base + kNoallocTilesOff, stage + kNoallocTilesOff, sizeof(int4) * total,
                                   hipMemcpyHostToDevice, st))) != hipSuccess)
         return hip_fail(e, "copying the batch tables");
     // the default shape's grid form: one wave per tile, or a persistent grid

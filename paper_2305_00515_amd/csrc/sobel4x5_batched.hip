@@ -163,34 +163,28 @@ const void *pick_batched(int ppl, int border, bool aligned, bool dir)
 
 }  // namespace
 
+// The split of an image's strips into tall and short row chunks (see
+// batched_tiles_each): tall chunks of `tallx` tile heights, the last
+// 1/`shortq` of the rows in chunks of one.  Tall chunks of 2 tile heights
+// measured best with the autotuned tile height (256 mixed images: 0.817 ms
+// against 0.836 for 4 and 0.876 for 8); SOBEL4X5_BATCH_TALLX and
+// SOBEL4X5_BATCH_SHORTQ override them (read once per process).
+BatchSplit batched_split()
+{
+    static const BatchSplit s = [] {
+        auto get = [](const char *name, int dflt) {
+            const char *v = std::getenv(name);
+            const int x = v ? std::atoi(v) : 0;
+            return x >= 1 && x <= 64 ? x : dflt;
+        };
+        return BatchSplit{get("SOBEL4X5_BATCH_TALLX", 2), get("SOBEL4X5_BATCH_SHORTQ", 4)};
+    }();
+    return s;
+}
+
 void batched_tiles(const U8Job &j, int32_t img, int th, std::vector<int4> &first, std::vector<int4> &last)
 {
-    // side-by-side strips: the top three quarters of the rows (rounded down
-    // to whole tall chunks of 2 th rows) in tall chunks, the rest in chunks
-    // of th rows, queued after every tall chunk of the batch.  Tall chunks of
-    // 2 th rows measured best with the autotuned th (256 mixed images:
-    // 0.817 ms against 0.836 for 4 th and 0.876 for 8 th);
-    // SOBEL4X5_BATCH_TALLX and SOBEL4X5_BATCH_SHORTQ (the 1/q of the rows in
-    // short chunks) override the split.
-    static const int tallx = [] {
-        const char *v = std::getenv("SOBEL4X5_BATCH_TALLX");
-        const int x = v ? std::atoi(v) : 0;
-        return x >= 1 && x <= 64 ? x : 2;
-    }();
-    static const int shortq = [] {
-        const char *v = std::getenv("SOBEL4X5_BATCH_SHORTQ");
-        const int x = v ? std::atoi(v) : 0;
-        return x >= 1 && x <= 64 ? x : 4;
-    }();
-    const int strips = j.ntx / 4, tall = tallx * th;
-    const int htall = (j.Ho - j.Ho / shortq) / tall * tall;
-    for (int y = 0; y < htall; y += tall)
-        for (int s = 0; s < strips; ++s) first.push_back(make_int4(img, tall << 1, 4 * s, y));
-    for (int y = htall; y < j.Ho; y += th)
-        for (int s = 0; s < strips; ++s) last.push_back(make_int4(img, th << 1, 4 * s, y));
-    // remaining tile columns: four row blocks stacked
-    for (int tx = 4 * strips; tx < j.ntx; ++tx)
-        for (int y = 0; y < j.Ho; y += 4 * th) first.push_back(make_int4(img, 1, tx, y));
+    batched_tiles_each(j, img, th, [&](int4 t) { first.push_back(t); }, [&](int4 t) { last.push_back(t); });
 }
 
 hipError_t launch_u8_batched(const U8Job *jobs, const int4 *tiles, int32_t total, uint32_t *queue, int border,
