@@ -4,6 +4,7 @@
 #include "u8_mfma.hpp"
 
 #include <algorithm>
+#include <cstring>
 #include <mutex>
 
 namespace s4x5 {
@@ -129,7 +130,16 @@ hipError_t launch_u8_mfma_weighted(const U8Job &j, int border, const int32_t *we
         const int32_t *w;
         int operator()(int f, int dy, int dx) const { return w[25 * f + 5 * dy + dx]; }
     };
-    MfmaWeights W = mfma_weights(Taps{weights});
+    // the operands of the last weights this thread launched with (a run of
+    // calls with the same kernels builds them once)
+    thread_local int32_t last[100];
+    thread_local MfmaWeights W;
+    thread_local bool have = false;
+    if (!have || std::memcmp(last, weights, sizeof(last)) != 0) {
+        W = mfma_weights(Taps{weights});
+        std::memcpy(last, weights, sizeof(last));
+        have = true;
+    }
     // without the clamp, 4 G^2 must stay below 2^31: |G| <= 128 sum|k| <= 23168
     int64_t most = 0;
     for (int f = 0; f < 4; ++f) {
