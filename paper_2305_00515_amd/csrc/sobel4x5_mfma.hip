@@ -35,22 +35,23 @@ __global__ __launch_bounds__(64 * kMWaves) __attribute__((amdgpu_waves_per_eu(4,
 }
 
 // Run-time kernels (weights fitting int8): the same sweep, weight operands
-// from the launch's arguments, no table (square-root rounding).
+// from the launch's arguments, no table (square-root rounding), so each
+// wave also stages its output tile in LDS for full-line stores.
 template <int OFF, int BM, bool CLAMP>
 __global__ __launch_bounds__(64 * kMWaves) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_u8_mfma_w(U8Job J, int nchunk,
                                                                                                      MfmaWeights W)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[kMWaves * kMTileBytes];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kMWaves * (kMTileBytes + kMOutBytes)];
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int ntx = (J.Wo + kMCols - 1) / kMCols, nty = (J.Ho + kMRows - 1) / kMRows;
     const int w = (int)blockIdx.x * kMWaves + wv;
     if (w >= ntx * nchunk) return;
     const int sx = w % ntx, ch = w / ntx;
     const int b0 = (int)((int64_t)ch * nty / nchunk), b1 = (int)((int64_t)(ch + 1) * nty / nchunk);
-    const u32 tile = (u32)(size_t)(LDS uint8_t *)lds + (u32)((wv & (kMWaves - 1)) * kMTileBytes);
+    const u32 base = (u32)(size_t)(LDS uint8_t *)lds + (u32)((wv & (kMWaves - 1)) * (kMTileBytes + kMOutBytes));
     v4i A[3];
     mfma_a_runtime(W, A);
-    mfma_strip<OFF, BM>(J, sx, b0, b1, tile, A, MagS<CLAMP>{});
+    mfma_strip<OFF, BM, MagS<CLAMP>, true>(J, sx, b0, b1, base, A, MagS<CLAMP>{}, base + kMTileBytes);
 }
 
 const void *mfma_fn(int border)

@@ -45,6 +45,7 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 typedef unsigned long long u64;
 typedef u32 u32_u __attribute__((aligned(1)));
 typedef v4i v4i_a8 __attribute__((aligned(8)));
+typedef gv4u gv4u_a8 __attribute__((aligned(8)));
 #define LDS __attribute__((address_space(3)))
 
 // The four filters of Eq. (sobel5_1), row dy top to bottom, column dx left
@@ -97,12 +98,15 @@ constexpr int kMCols = 8 * kMGroups;   // output columns of a tile
 constexpr int kMInRows = kMRows + 4;   // input rows a tile reads
 constexpr int kMInLead = 12;           // input columns before the tile's first output column
 constexpr int kMPieces = 9;            // 16-byte pieces of an input row: columns [X - 12, X + 132)
-constexpr int kMPitch = 168;           // LDS row pitch: 42 dwords, 8-byte reads of 32 rows hit distinct banks
+constexpr int kMPitch = 152;           // LDS row pitch: 38 dwords, 8-byte reads of 32 rows hit distinct banks
+constexpr int kMOutPitch = 136;        // staged output rows (STAGE): 34 dwords, a dword a lane per row
+constexpr int kMOutBytes = kMRows * kMOutPitch;
 constexpr int kMTileBytes = kMInRows * kMPitch;
 constexpr int kMWaves = 8;             // waves per workgroup (one table copy for eight tiles)
 static_assert(16 * kMPieces == kMInLead + kMCols + 4, "input row = lead + outputs + right halo");
 static_assert(kMPitch % 8 == 0 && kMPitch >= 16 * kMPieces, "row pitch");
-static_assert(kLutTSize + kMWaves * kMTileBytes <= 81920, "two workgroups per CU");
+static_assert(kLutTSize + kMWaves * kMTileBytes <= 81920, "two workgroups per CU (with the T table)");
+static_assert(kMWaves * (kMTileBytes + kMOutBytes) <= 81920, "two workgroups per CU (staged outputs)");
 
 // Weight operands of the three products for every lane: 16 bytes each,
 // k = 16 (lane / 32) + byte, from four 5x5 kernels k[f][dy][dx] whose
@@ -376,8 +380,16 @@ struct MagS {
 // lane (n, 0) holds columns 8j .. 8j + 15 and lane (n, 1) 8j + 16 ..
 // 8j + 31: one 16-byte store each, instead of four 4-byte stores that
 // would reach L2 as 8-byte pieces of 32 rows.
-template <bool FULL, class Mag>
-__device__ __forceinline__ void mfma_tile(const U8Job &J, int y0, int X, u32 tile, const v4i (&A)[3], const Mag &mag)
+//
+// STAGE (kernels with LDS to spare): each group's dwords go to the wave's
+// output tile in LDS instead (row n, bytes 8j + 4h), and after the 16
+// groups every row leaves as eight 16-byte stores by eight lanes, one full
+// 128-byte line: the permlane form writes each line in four 32-byte pieces
+// from four instructions, and those partial lines cost about 1.4x the
+// output bytes in HBM writes.
+template <bool FULL, class Mag, bool STAGE>
+__device__ __forceinline__ void mfma_tile(const U8Job &J, int y0, int X, u32 tile, u32 otile, const v4i (&A)[3],
+                                          const Mag &mag)
 {
     // a fresh base each tile, so that the 48 operand addresses of the tile
     // are the three row bases plus immediate offsets, not registers held
@@ -409,6 +421,9 @@ __device__ __forceinline__ void mfma_tile(const U8Job &J, int y0, int X, u32 til
             }
         }
     };
+    // rows 16..31 keep their two dwords of each group swapped: a half-wave
+    // of writes (rows 0..31, one h) then covers 32 distinct banks
+    LDS u32 *orow_lds = (LDS u32 *)(size_t)(otile + (u32)(n * kMOutPitch + 4 * (h ^ (n >> 4))));
     v4i B[3];
     mfma_load_b(rb, 0, B);
     v16i Dn = mfma_products(A, B);
@@ -422,15 +437,47 @@ __device__ __forceinline__ void mfma_tile(const U8Job &J, int y0, int X, u32 til
         u32 mb[4];
         mag.lookup(D, mb);
         if (j > 0) {
-            out[(j - 1) & 3] = mag.pack(mbp);
-            if (((j - 1) & 3) == 3) store4(out, j - 4);
+            if constexpr (STAGE) {
+                orow_lds[2 * (j - 1)] = mag.pack(mbp);
+            } else {
+                out[(j - 1) & 3] = mag.pack(mbp);
+                if (((j - 1) & 3) == 3) store4(out, j - 4);
+            }
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) mbp[i] = mb[i];
         __builtin_amdgcn_sched_barrier(0);
     }
-    out[3] = mag.pack(mbp);
-    store4(out, kMGroups - 4);
+    if constexpr (!STAGE) {
+        out[3] = mag.pack(mbp);
+        store4(out, kMGroups - 4);
+        return;
+    }
+    orow_lds[2 * (kMGroups - 1)] = mag.pack(mbp);
+    // the rows were written by the two lanes that hold them
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    const int col = 16 * (lane & 7);
+#pragma unroll
+    for (int k = 0; k < kMRows / 8; ++k) {
+        const int r = (lane >> 3) + 8 * k;
+        gv4u v = *(const LDS gv4u_a8 *)(size_t)(otile + (u32)(r * kMOutPitch + col));
+        if (k >= 2) v = gv4u{v.y, v.x, v.w, v.z};   // rows 16..31
+        const int y = y0 + r;
+        GMEM uint8_t *p = (GMEM uint8_t *)J.mag + (int64_t)(FULL || y < J.Ho ? y : 0) * J.mag_pitch + X + col;
+        if (FULL) {
+            *reinterpret_cast<GMEM gv4u_u *>(p) = v;
+        } else if (y < J.Ho) {
+            const int nvalid = J.Wo - X - col;
+            if (nvalid >= 16) {
+                *reinterpret_cast<GMEM gv4u_u *>(p) = v;
+            } else {
+                const u32 w[4] = {v.x, v.y, v.z, v.w};
+                for (int q = 0; q < nvalid; ++q) p[q] = (uint8_t)(w[q >> 2] >> (8 * (q & 3)));
+            }
+        }
+    }
+    // the next tile's writes to this output tile come after these reads
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
 // One wave: tiles [b0, b1) of column strip sx, top to bottom, in the LDS
@@ -438,9 +485,9 @@ __device__ __forceinline__ void mfma_tile(const U8Job &J, int y0, int X, u32 til
 // rows are fetched into registers while the tile before it is computed,
 // then written to LDS; the tiles at the image edges load through the border
 // rule in between.
-template <int OFF, int BM, class Mag>
+template <int OFF, int BM, class Mag, bool STAGE = false>
 __device__ __forceinline__ void mfma_strip(const U8Job &J, int sx, int b0, int b1, u32 tile, const v4i (&A)[3],
-                                           const Mag &mag)
+                                           const Mag &mag, u32 otile = 0)
 {
     const int X = sx * kMCols;
     const bool cols_full = X + kMCols <= J.Wo;
@@ -462,9 +509,9 @@ __device__ __forceinline__ void mfma_strip(const U8Job &J, int sx, int b0, int b
         // the tile's rows were written by other lanes of this wave
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         if (cols_full && y0 + kMRows <= J.Ho)
-            mfma_tile<true>(J, y0, X, tile, A, mag);
+            mfma_tile<true, Mag, STAGE>(J, y0, X, tile, otile, A, mag);
         else
-            mfma_tile<false>(J, y0, X, tile, A, mag);
+            mfma_tile<false, Mag, STAGE>(J, y0, X, tile, otile, A, mag);
         // every operand read of this tile has returned (the products and
         // stores consumed them) before its rows are overwritten
         if (fetch_next)
