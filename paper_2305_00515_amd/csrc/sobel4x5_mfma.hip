@@ -31,7 +31,7 @@ __global__ __launch_bounds__(64 * kMWaves) __attribute__((amdgpu_waves_per_eu(4,
     const u32 tile = (u32)(size_t)(LDS uint8_t *)lds + (u32)(kLutTSize + (wv & (kMWaves - 1)) * kMTileBytes);
     v4i A[3];
     mfma_a_default(A);
-    mfma_strip<OFF, BM>(J, sx, b0, b1, tile, A, MagT{(const LDS uint8_t *)lds});
+    mfma_strip<OFF, BM, MagT, kStageInPlace>(J, sx, b0, b1, tile, A, MagT{(const LDS uint8_t *)lds}, tile);
 }
 
 // Run-time kernels (weights fitting int8): the same sweep, weight operands
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(64 * kMWaves) __attribute__((amdgpu_waves_per_eu(4,
     const u32 base = (u32)(size_t)(LDS uint8_t *)lds + (u32)((wv & (kMWaves - 1)) * (kMTileBytes + kMOutBytes));
     v4i A[3];
     mfma_a_runtime(W, A);
-    mfma_strip<OFF, BM, MagS<CLAMP>, true>(J, sx, b0, b1, base, A, MagS<CLAMP>{}, base + kMTileBytes);
+    mfma_strip<OFF, BM, MagS<CLAMP>, kStageOwn>(J, sx, b0, b1, base, A, MagS<CLAMP>{}, base + kMTileBytes);
 }
 
 const void *mfma_fn(int border)

@@ -31,7 +31,7 @@
 // A lane of D holds, for its output row n = lane % 32 and half
 // h = lane / 32, the four responses of columns 4h .. 4h + 3 of the group:
 // its four magnitude bytes are one contiguous dword of the output row.
-// Requires v_permlane32_swap (gfx950) for the output stores.
+// Requires gfx950 (the 32x32x32 int8 products).
 #pragma once
 
 #include "load_columns.hpp"
@@ -99,8 +99,10 @@ constexpr int kMInRows = kMRows + 4;   // input rows a tile reads
 constexpr int kMInLead = 12;           // input columns before the tile's first output column
 constexpr int kMPieces = 9;            // 16-byte pieces of an input row: columns [X - 12, X + 132)
 constexpr int kMPitch = 152;           // LDS row pitch: 38 dwords, 8-byte reads of 32 rows hit distinct banks
-constexpr int kMOutPitch = 136;        // staged output rows (STAGE): 34 dwords, a dword a lane per row
+constexpr int kMOutPitch = 136;        // staged output rows of their own: 34 dwords
 constexpr int kMOutBytes = kMRows * kMOutPitch;
+// Where a tile's outputs wait for their full-line stores (see mfma_tile).
+constexpr int kStageOwn = 1, kStageInPlace = 2;
 constexpr int kMTileBytes = kMInRows * kMPitch;
 constexpr int kMWaves = 8;             // waves per workgroup (one table copy for eight tiles)
 static_assert(16 * kMPieces == kMInLead + kMCols + 4, "input row = lead + outputs + right halo");
@@ -371,26 +373,28 @@ struct MagS {
 // `tile`).  FULL: every output of the tile lies inside the image.  Pipeline
 // over the 16 column groups: in step j the products of group j + 1 run, the
 // operands of group j + 2 load, group j's table reads are issued and group
-// j - 1's bytes (read in step j - 1) are packed and stored.
+// j - 1's bytes (read in step j - 1) are packed.
 //
-// Stores: after group j, lane (n, 0) holds the magnitude bytes of columns
-// 8j .. 8j + 3 of row n and lane (n, 1) those of 8j + 4 .. 8j + 7.  Every
-// four groups two v_permlane32_swap exchange the upper half's dwords of
-// groups j, j + 1 with the lower half's of groups j + 2, j + 3, so that
-// lane (n, 0) holds columns 8j .. 8j + 15 and lane (n, 1) 8j + 16 ..
-// 8j + 31: one 16-byte store each, instead of four 4-byte stores that
-// would reach L2 as 8-byte pieces of 32 rows.
-//
-// STAGE (kernels with LDS to spare): each group's dwords go to the wave's
-// output tile in LDS instead (row n, bytes 8j + 4h), and after the 16
-// groups every row leaves as eight 16-byte stores by eight lanes, one full
-// 128-byte line: the permlane form writes each line in four 32-byte pieces
-// from four instructions, and those partial lines cost about 1.4x the
-// output bytes in HBM writes.
-template <bool FULL, class Mag, bool STAGE>
+// Stores: after group j, lane (n, h) holds the magnitude bytes of columns
+// 8j + 4h .. 8j + 4h + 3 of row n.  They wait in an output tile in LDS (row
+// n, bytes 8j + 4h), and after the 16 groups every row leaves as eight
+// 16-byte stores by eight lanes, one full 128-byte line.  Stored straight
+// from the lanes (even four groups at a time, 16 bytes a lane after two
+// v_permlane32_swap), each line leaves in 32-byte pieces from several
+// instructions, and those partial lines cost about 1.4x the output bytes in
+// HBM writes.  Rows 16..31 keep each group's two dwords swapped, so that a
+// half-wave of writes (rows 0..31, one h) covers 32 distinct banks.
+//   kStageOwn: an output tile of its own (pitch kMOutPitch);
+//   kStageInPlace: the input tile itself (pitch kMPitch).  Group j's
+//   outputs land in bytes [8j, 8j + 8) of rows 0..31, written after group
+//   j's products: the operand reads of group j and later groups start at
+//   byte 8j + 8 of a row, and those of earlier groups were consumed by
+//   their products already.
+template <bool FULL, class Mag, int STAGE>
 __device__ __forceinline__ void mfma_tile(const U8Job &J, int y0, int X, u32 tile, u32 otile, const v4i (&A)[3],
                                           const Mag &mag)
 {
+    static_assert(STAGE == kStageOwn || STAGE == kStageInPlace, "output staging");
     // a fresh base each tile, so that the 48 operand addresses of the tile
     // are the three row bases plus immediate offsets, not registers held
     // across tiles
@@ -400,35 +404,13 @@ __device__ __forceinline__ void mfma_tile(const U8Job &J, int y0, int X, u32 til
     const MfmaRows rb{(const LDS uint8_t *)(size_t)(tile + (u32)((n + h) * kMPitch + 8)),
                       (const LDS uint8_t *)(size_t)(tile + (u32)((n + 2 + h) * kMPitch + 8)),
                       (const LDS uint8_t *)(size_t)(tile + (u32)((n + 4) * kMPitch + 8))};
-    const int yo = y0 + n;
-    const bool row_ok = FULL || yo < J.Ho;
-    GMEM uint8_t *orow = (GMEM uint8_t *)J.mag + (int64_t)(row_ok ? yo : 0) * J.mag_pitch + X + 16 * h;
-    const int nvalid0 = J.Wo - X - 16 * h;
-    auto store4 = [&](const u32 (&out)[4], int j0) __attribute__((always_inline)) {
-        const auto s02 = __builtin_amdgcn_permlane32_swap(out[0], out[2], false, false);
-        const auto s13 = __builtin_amdgcn_permlane32_swap(out[1], out[3], false, false);
-        const gv4u v = {s02[0], s02[1], s13[0], s13[1]};
-        const int c = 8 * j0;   // first column of the lane's 16 bytes, from X + 16 h
-        if (FULL) {
-            *reinterpret_cast<GMEM gv4u_u *>(orow + c) = v;
-        } else if (row_ok) {
-            const int nvalid = nvalid0 - c;
-            if (nvalid >= 16) {
-                *reinterpret_cast<GMEM gv4u_u *>(orow + c) = v;
-            } else {
-                const u32 w[4] = {v.x, v.y, v.z, v.w};
-                for (int q = 0; q < nvalid; ++q) orow[c + q] = (uint8_t)(w[q >> 2] >> (8 * (q & 3)));
-            }
-        }
-    };
-    // rows 16..31 keep their two dwords of each group swapped: a half-wave
-    // of writes (rows 0..31, one h) then covers 32 distinct banks
-    LDS u32 *orow_lds = (LDS u32 *)(size_t)(otile + (u32)(n * kMOutPitch + 4 * (h ^ (n >> 4))));
+    constexpr int OP = STAGE == kStageInPlace ? kMPitch : kMOutPitch;
+    LDS u32 *orow_lds = (LDS u32 *)(size_t)(otile + (u32)(n * OP + 4 * (h ^ (n >> 4))));
     v4i B[3];
     mfma_load_b(rb, 0, B);
     v16i Dn = mfma_products(A, B);
     mfma_load_b(rb, 1, B);
-    u32 out[4], mbp[4];
+    u32 mbp[4];
 #pragma unroll
     for (int j = 0; j < kMGroups; ++j) {
         const v16i D = Dn;
@@ -436,22 +418,10 @@ __device__ __forceinline__ void mfma_tile(const U8Job &J, int y0, int X, u32 til
         if (j + 2 < kMGroups) mfma_load_b(rb, j + 2, B);
         u32 mb[4];
         mag.lookup(D, mb);
-        if (j > 0) {
-            if constexpr (STAGE) {
-                orow_lds[2 * (j - 1)] = mag.pack(mbp);
-            } else {
-                out[(j - 1) & 3] = mag.pack(mbp);
-                if (((j - 1) & 3) == 3) store4(out, j - 4);
-            }
-        }
+        if (j > 0) orow_lds[2 * (j - 1)] = mag.pack(mbp);
 #pragma unroll
         for (int i = 0; i < 4; ++i) mbp[i] = mb[i];
         __builtin_amdgcn_sched_barrier(0);
-    }
-    if constexpr (!STAGE) {
-        out[3] = mag.pack(mbp);
-        store4(out, kMGroups - 4);
-        return;
     }
     orow_lds[2 * (kMGroups - 1)] = mag.pack(mbp);
     // the rows were written by the two lanes that hold them
@@ -460,7 +430,7 @@ __device__ __forceinline__ void mfma_tile(const U8Job &J, int y0, int X, u32 til
 #pragma unroll
     for (int k = 0; k < kMRows / 8; ++k) {
         const int r = (lane >> 3) + 8 * k;
-        gv4u v = *(const LDS gv4u_a8 *)(size_t)(otile + (u32)(r * kMOutPitch + col));
+        gv4u v = *(const LDS gv4u_a8 *)(size_t)(otile + (u32)(r * OP + col));
         if (k >= 2) v = gv4u{v.y, v.x, v.w, v.z};   // rows 16..31
         const int y = y0 + r;
         GMEM uint8_t *p = (GMEM uint8_t *)J.mag + (int64_t)(FULL || y < J.Ho ? y : 0) * J.mag_pitch + X + col;
@@ -476,7 +446,7 @@ __device__ __forceinline__ void mfma_tile(const U8Job &J, int y0, int X, u32 til
             }
         }
     }
-    // the next tile's writes to this output tile come after these reads
+    // the next tile's writes to this LDS come after these reads
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
@@ -485,9 +455,9 @@ __device__ __forceinline__ void mfma_tile(const U8Job &J, int y0, int X, u32 til
 // rows are fetched into registers while the tile before it is computed,
 // then written to LDS; the tiles at the image edges load through the border
 // rule in between.
-template <int OFF, int BM, class Mag, bool STAGE = false>
+template <int OFF, int BM, class Mag, int STAGE>
 __device__ __forceinline__ void mfma_strip(const U8Job &J, int sx, int b0, int b1, u32 tile, const v4i (&A)[3],
-                                           const Mag &mag, u32 otile = 0)
+                                           const Mag &mag, u32 otile)
 {
     const int X = sx * kMCols;
     const bool cols_full = X + kMCols <= J.Wo;
