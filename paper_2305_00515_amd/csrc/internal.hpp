@@ -113,6 +113,10 @@ void batched_tiles_each(const U8Job &j, int32_t img, int th, First &&first, Last
 // The same into two vectors.
 void batched_tiles(const U8Job &j, int32_t img, int th, std::vector<int4> &first, std::vector<int4> &last);
 
+// Reorders tiles [b, e) of a static-grid table so that each XCD's
+// workgroups take a contiguous stretch of it (sobel4x5_batched.hip).
+void xcd_order(std::vector<int4> &v, size_t b, size_t e);
+
 // Allocation-free batched call (sobel4x5_batched_noalloc): the queue
 // words, the job table and the tile table of one batch live in a fixed
 // device buffer of kNoallocBytes per device, laid out as below.  The limits

@@ -399,7 +399,12 @@ int plan_setup(sobel4x5_plan_s *p, const U8Shape &shape)
         batched_tiles(jobs[i], i, shape.th, tiles, tail);
         if (tiles.size() + tail.size() > (size_t)INT32_MAX) return fail(SOBEL4X5_EINVAL, "batch too large for one plan");
     }
+    const size_t nfirst = tiles.size();
     tiles.insert(tiles.end(), tail.begin(), tail.end());
+    if (shape.waves == kStaticGrid) {
+        xcd_order(tiles, 0, nfirst);
+        xcd_order(tiles, nfirst, tiles.size());
+    }
     p->total = (int32_t)tiles.size();
     hipError_t e;
     if ((e = hipMalloc(&p->d_jobs, sizeof(U8Job) * p->count)) != hipSuccess ||

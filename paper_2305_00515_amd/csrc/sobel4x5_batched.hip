@@ -4,6 +4,7 @@
 
 #include "u8_sweep.hpp"
 
+#include <algorithm>
 #include <cstdlib>
 #include <mutex>
 
@@ -185,6 +186,32 @@ BatchSplit batched_split()
 void batched_tiles(const U8Job &j, int32_t img, int th, std::vector<int4> &first, std::vector<int4> &last)
 {
     batched_tiles_each(j, img, th, [&](int4 t) { first.push_back(t); }, [&](int4 t) { last.push_back(t); });
+}
+
+// Static grid: workgroup g (four wave-tiles, in dispatch order) runs on XCD
+// g mod 8, so in the table order the workgroups that share an XCD's L2 are
+// eight apart, and a row band's neighbours above and to the side (whose
+// halo rows and columns it reads again) sit on other XCDs.  Reordered,
+// XCD x takes the x-th of eight contiguous stretches of [b, e) (whole
+// workgroups of the table order, the ones left over stay at the end), and
+// the rows those neighbours read come from its own L2.  SOBEL4X5_BATCH_XCD=0
+// keeps the table order (read once per process).
+void xcd_order(std::vector<int4> &v, size_t b, size_t e)
+{
+    static const bool on = [] {
+        const char *s = std::getenv("SOBEL4X5_BATCH_XCD");
+        return !(s && std::atoi(s) == 0);
+    }();
+    constexpr size_t kX = 8, kG = kWaves;
+    const size_t ng = (e - b) / kG;
+    if (!on || ng < 2 * kX) return;
+    std::vector<int4> src(v.begin() + b, v.begin() + b + ng * kG);
+    size_t start[kX + 1] = {0};
+    for (size_t x = 0; x < kX; ++x) start[x + 1] = start[x] + (ng - x + kX - 1) / kX;   // groups g = x mod 8
+    for (size_t g = 0; g < ng; ++g) {
+        const size_t from = start[g % kX] + g / kX;
+        std::copy(src.begin() + from * kG, src.begin() + (from + 1) * kG, v.begin() + b + g * kG);
+    }
 }
 
 hipError_t launch_u8_batched(const U8Job *jobs, const int4 *tiles, int32_t total, uint32_t *queue, int border,
