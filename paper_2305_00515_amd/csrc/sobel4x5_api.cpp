@@ -401,9 +401,9 @@ int plan_setup(sobel4x5_plan_s *p, const U8Shape &shape)
     }
     const size_t nfirst = tiles.size();
     tiles.insert(tiles.end(), tail.begin(), tail.end());
-    if (shape.waves == kStaticGrid) {
+    if (shape.waves == kStaticGrid) {   // each part from a workgroup boundary (4 tiles)
         xcd_order(tiles, 0, nfirst);
-        xcd_order(tiles, nfirst, tiles.size());
+        xcd_order(tiles, std::min(tiles.size(), (nfirst + 3) / 4 * 4), tiles.size());
     }
     p->total = (int32_t)tiles.size();
     hipError_t e;

@@ -192,10 +192,12 @@ void batched_tiles(const U8Job &j, int32_t img, int th, std::vector<int4> &first
 // g mod 8, so in the table order the workgroups that share an XCD's L2 are
 // eight apart, and a row band's neighbours above and to the side (whose
 // halo rows and columns it reads again) sit on other XCDs.  Reordered,
-// XCD x takes the x-th of eight contiguous stretches of [b, e) (whole
+// each XCD takes one of eight contiguous stretches of [b, e) (whole
 // workgroups of the table order, the ones left over stay at the end), and
-// the rows those neighbours read come from its own L2.  SOBEL4X5_BATCH_XCD=0
-// keeps the table order (read once per process).
+// the rows those neighbours read come from its own L2.  b is a multiple of
+// four, so the workgroups of [b, e) start at a workgroup boundary and each
+// residue of their index mod 8 is one XCD.  SOBEL4X5_BATCH_XCD=0 keeps the
+// table order (read once per process).
 void xcd_order(std::vector<int4> &v, size_t b, size_t e)
 {
     static const bool on = [] {
