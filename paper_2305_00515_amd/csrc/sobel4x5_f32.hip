@@ -244,23 +244,14 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_fwd(F32Args a, int 
     char *dst = reinterpret_cast<char *>(a.out) + (int64_t)b * a.out_bstride;
     const int64_t oa = (int64_t)(ox < 0 ? 0 : ox) * 4;
     const int r0 = o0 + OFF - 2;
-    // wave-uniform: every lane's column pair inside the image, 8-byte rows
-    // (a pair is one 8-byte load)
-    const int cx0 = s * kOwnF - kHaloF + OFF;                 // input column of lane 0's element a
-    const bool vec = cx0 >= 0 && cx0 + 128 <= a.W &&
-                     ((reinterpret_cast<uintptr_t>(src) | (uintptr_t)a.src_pitch) & 7u) == 0;
     // both kept columns stored with one 8-byte store
     const bool vst = keep_a && keep_b && ((reinterpret_cast<uintptr_t>(dst) | (uintptr_t)a.out_pitch) & 7u) == 0;
+    // a pair is two 4-byte loads at the lane's border-mapped columns (see
+    // the adjoint's loads)
     auto ld = [&](int t) {
         const int r = r0 + t;
         const char *row = src + (int64_t)edge_index<BM>(r, a.H) * a.src_pitch;
-        F2 v;
-        if (vec) {
-            const float2 w = *reinterpret_cast<const float2 *>(row + xa);
-            v = F2{w.x, w.y};
-        } else {
-            v = F2{*reinterpret_cast<const float *>(row + xa), *reinterpret_cast<const float *>(row + xb)};
-        }
+        F2 v{*reinterpret_cast<const float *>(row + xa), *reinterpret_cast<const float *>(row + xb)};
         if constexpr (BM == kZero) {
             const bool rin = r >= 0 && r < a.H;
             v = F2{rin && ina ? v.a : 0.f, rin && inb ? v.b : 0.f};
@@ -365,43 +356,31 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void k_f32_bwd(F32Args a, int 
     const int r0 = X0 - ((kFold && X0 == 0) ? 6 : 4);
     const int T = X1 + ((kFold && X1 == a.H) ? 6 : 4) - r0;
 
-    // Wave-uniform: every lane's column pair lies inside the image (and, for
-    // grad, inside the output) and the rows are 8-byte aligned, so a pair is
-    // one 8-byte load (xb = xa + 4, gb = ga + 4, all lanes centred).
-    const bool vecx = c0 >= 0 && c0 + 128 <= a.W &&
-                      ((reinterpret_cast<uintptr_t>(src) | (uintptr_t)a.src_pitch) & 7u) == 0;
-    const bool vecg = c0 - OFF >= 0 && c0 + 128 - OFF <= a.Wo &&
-                      ((reinterpret_cast<uintptr_t>(gr) | (uintptr_t)a.g_pitch) & 7u) == 0;
     auto ldx = [&](int t) {
         const int r = r0 + t;
         const char *row = src + (int64_t)edge_index<BM>(r, a.H) * a.src_pitch;
-        F2 v;
-        if (vecx) {
-            const float2 w = *reinterpret_cast<const float2 *>(row + xa);
-            v = F2{w.x, w.y};
-        } else {
-            v = F2{*reinterpret_cast<const float *>(row + xa), *reinterpret_cast<const float *>(row + xb)};
-        }
+        // two 4-byte loads at the lane's border-mapped columns (inside the
+        // image xb = xa + 4).  An 8-byte load for waves whose pairs all lie
+        // inside took the same VALU count or more: behind the wave-uniform
+        // choice the compiler computed both addresses and selected between
+        // them on every row (adjoint interior loop: 1074 against 946 VALU
+        // instructions per 5 rows).
+        F2 v{*reinterpret_cast<const float *>(row + xa), *reinterpret_cast<const float *>(row + xb)};
         if constexpr (BM == kZero) {
             const bool rin = r >= 0 && r < a.H;
             v = F2{rin && ina ? v.a : 0.f, rin && inb ? v.b : 0.f};
         }
         return v;
     };
-    // grad of the output row whose centre is input row r0 + t - 2 (0 outside)
+    // grad of the output row whose centre is input row r0 + t - 2 (0 outside;
+    // ga, gb are clamped columns, masked where no output pixel is centred)
     auto ldg = [&](int t) {
         const int o = r0 + t - 2 - OFF;
         F2 v{0.f, 0.f};
         if (o >= 0 && o < a.Ho) {
             const char *row = gr + (int64_t)o * a.g_pitch;
-            if (vecg) {
-                const float2 w = *reinterpret_cast<const float2 *>(row + ga);
-                v = F2{w.x, w.y};
-            } else {
-                v = F2{*reinterpret_cast<const float *>(row + ga), *reinterpret_cast<const float *>(row + gb)};
-            }
+            v = F2{*reinterpret_cast<const float *>(row + ga), *reinterpret_cast<const float *>(row + gb)};
         }
-        if (vecg) return v;
         return F2{oc_a ? v.a : 0.f, oc_b ? v.b : 0.f};
     };
 
