@@ -478,7 +478,7 @@ def bench_copy(torch, api, dev, steps):
 #   valu:    VALU instructions per output pixel (SQ_INSTS_VALU x 64 / pixels
 #            from the same profile; the kernel has no transcendental
 #            instruction, so each is one issue slot).
-U8_PROFILE = {"src_sha256": "af4bc8a9e436e43b", "traffic_bytes": 145385472, "valu_slots_per_px": 21434880 * 64 / 8192.0 ** 2}
+U8_PROFILE = {"src_sha256": "5c30fa8417524d3a", "traffic_bytes": 145362304, "valu_slots_per_px": 21434880 * 64 / 8192.0 ** 2}
 
 
 # Sources k_u8_single is compiled from (the hash covers them in this order);

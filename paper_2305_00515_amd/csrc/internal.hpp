@@ -39,6 +39,7 @@ struct U8Shape {
     int waves = 0;  // single-image kernel: waves to launch (0 = all resident waves)
     int min_rows = 2;   // single-image kernel: fewest output rows per wave (small images are latency-bound)
     bool sep = false;   // four-directional magnitudes in the separable form (the kernel that also serves planes)
+    int tallx = 0;      // batched kernel: tall chunks of tallx tile heights (0: batched_split())
 };
 
 // True when the fast (vector-load) kernel may read this image: 16-byte
@@ -97,10 +98,10 @@ struct BatchSplit {
 BatchSplit batched_split();
 
 template <class First, class Last>
-void batched_tiles_each(const U8Job &j, int32_t img, int th, First &&first, Last &&last)
+void batched_tiles_each(const U8Job &j, int32_t img, int th, int tallx, First &&first, Last &&last)
 {
     const BatchSplit sp = batched_split();
-    const int strips = j.ntx / 4, tall = sp.tallx * th;
+    const int strips = j.ntx / 4, tall = (tallx > 0 ? tallx : sp.tallx) * th;
     const int htall = (j.Ho - j.Ho / sp.shortq) / tall * tall;
     for (int y = 0; y < htall; y += tall)
         for (int s = 0; s < strips; ++s) first(make_int4(img, tall << 1, 4 * s, y));
@@ -111,7 +112,8 @@ void batched_tiles_each(const U8Job &j, int32_t img, int th, First &&first, Last
 }
 
 // The same into two vectors.
-void batched_tiles(const U8Job &j, int32_t img, int th, std::vector<int4> &first, std::vector<int4> &last);
+void batched_tiles(const U8Job &j, int32_t img, int th, int tallx, std::vector<int4> &first,
+                   std::vector<int4> &last);
 
 // Reorders tiles [b, e) of a static-grid table so that each XCD's
 // workgroups take a contiguous stretch of it (sobel4x5_batched.hip).

@@ -396,7 +396,7 @@ int plan_setup(sobel4x5_plan_s *p, const U8Shape &shape)
     p->aligned = aligned;
     std::vector<int4> tiles, tail;
     for (int32_t i = 0; i < p->count; ++i) {
-        batched_tiles(jobs[i], i, shape.th, tiles, tail);
+        batched_tiles(jobs[i], i, shape.th, shape.tallx, tiles, tail);
         if (tiles.size() + tail.size() > (size_t)INT32_MAX) return fail(SOBEL4X5_EINVAL, "batch too large for one plan");
     }
     const size_t nfirst = tiles.size();
@@ -593,17 +593,19 @@ bool tune_lookup(const std::string &key, U8Shape &s)
 {
     FILE *f = std::fopen(tune_cache_path().c_str(), "r");
     if (!f) return false;
-    // one entry a line: key ppl th wpg [static]; a line without the last
-    // field is a persistent grid
+    // one entry a line: key ppl th wpg [static [tallx]]; a line without
+    // the static field is a persistent grid, one without tallx takes the
+    // default split
     char line[1024], k[512];
     bool found = false;
     while (std::fgets(line, sizeof line, f)) {
-        int ppl = 0, th = 0, wpg = 0, st = 0;
-        const int n = std::sscanf(line, "%511s %d %d %d %d", k, &ppl, &th, &wpg, &st);
+        int ppl = 0, th = 0, wpg = 0, st = 0, tx = 0;
+        const int n = std::sscanf(line, "%511s %d %d %d %d %d", k, &ppl, &th, &wpg, &st, &tx);
         if (n >= 4 && key == k && (ppl == 8 || ppl == 16) && th >= 4 && th <= 256 && wpg == 4 &&
-            (st == 0 || st == 1)) {
+            (st == 0 || st == 1) && tx >= 0 && tx <= 64) {
             s = U8Shape{ppl, th, wpg};
-            if (n == 5 && st == 1) s.waves = kStaticGrid;
+            if (n >= 5 && st == 1) s.waves = kStaticGrid;
+            if (n == 6) s.tallx = tx;
             found = true;   // last entry wins
         }
     }
@@ -618,7 +620,7 @@ void tune_store(const std::string &key, const U8Shape &s)
     if (slash != std::string::npos && slash > 0) mkdir(path.substr(0, slash).c_str(), 0755);   // best effort
     FILE *f = std::fopen(path.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), s.ppl, s.th, s.wpg, s.waves == kStaticGrid ? 1 : 0);
+    std::fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), s.ppl, s.th, s.wpg, s.waves == kStaticGrid ? 1 : 0, s.tallx);
     std::fclose(f);
 }
 
@@ -716,6 +718,22 @@ int plan_autotune(sobel4x5_plan_s *p)
                     best = c;
                 }
             }
+    // then the height of the tall chunks around the best shape (the default
+    // split takes 2 tile heights)
+    for (int tx : {1, 4}) {
+        U8Shape c = best;
+        c.tallx = tx;
+        int rc;
+        if (!candidate_matches(p, c, want, &rc)) {
+            if (rc != SOBEL4X5_OK) return rc;
+            continue;
+        }
+        const double ms = time_plan(p, 10);
+        if (ms > 0 && ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
     tune_store(key, best);
     return plan_setup(p, best);
 }
@@ -1082,7 +1100,7 @@ int sobel4x5_batched_noalloc(const sobel4x5_image *imgs, int32_t count, int32_t 
         aligned = aligned && u8_rows_aligned(j) && !(border == SOBEL4X5_BORDER_REFLECT101 && m.width < 3);
         std::memcpy(stage + kNoallocJobsOff + sizeof(U8Job) * i, &j, sizeof(U8Job));
         batched_tiles_each(
-            j, i, shape.th,
+            j, i, shape.th, shape.tallx,
             [&](int4 t) {
                 if (nfirst + ntail < kNoallocMaxTiles) first[nfirst++] = t; else over = true;
             },

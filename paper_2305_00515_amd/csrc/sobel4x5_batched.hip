@@ -194,9 +194,10 @@ BatchSplit batched_split()
     return s;
 }
 
-void batched_tiles(const U8Job &j, int32_t img, int th, std::vector<int4> &first, std::vector<int4> &last)
+void batched_tiles(const U8Job &j, int32_t img, int th, int tallx, std::vector<int4> &first,
+                   std::vector<int4> &last)
 {
-    batched_tiles_each(j, img, th, [&](int4 t) { first.push_back(t); }, [&](int4 t) { last.push_back(t); });
+    batched_tiles_each(j, img, th, tallx, [&](int4 t) { first.push_back(t); }, [&](int4 t) { last.push_back(t); });
 }
 
 // Static grid: workgroup g (four wave-tiles, in dispatch order) runs on XCD

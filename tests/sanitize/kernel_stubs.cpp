@@ -21,7 +21,7 @@ hipError_t launch_u8_batched(const U8Job *, const int4 *, int32_t, uint32_t *, i
 {
     return hipErrorNoDevice;
 }
-void batched_tiles(const U8Job &, int32_t, int, std::vector<int4> &, std::vector<int4> &) {}
+void batched_tiles(const U8Job &, int32_t, int, int, std::vector<int4> &, std::vector<int4> &) {}
 BatchSplit batched_split() { return BatchSplit{2, 4}; }
 void xcd_order(std::vector<int4> &, size_t, size_t) {}
 int u8_persistent_grid(const U8Shape &, int, bool, bool) { return 0; }
